@@ -1,0 +1,192 @@
+/*
+ * geosstv.h - C ABI of the MI355X (gfx950) GeoSSTV denoising-and-destriping
+ * solver: the preconditioned primal-dual splitting (P-PDS) iteration of
+ * Alg. 1 in Takemoto and Ono, "Geometric Spatio-Spectral Total Variation for
+ * Hyperspectral Image Denoising and Destriping", applied to problem (20)
+ * (the split form of the constrained problem (15)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Cube layout. Band-sequential (BSQ): element (i, j, k) of the N1 x N2 x N3
+ *   cube (i vertical pixel, j horizontal pixel, k band; Sec. II-A) is at
+ *   index (k*N1 + i)*N2 + j of a float array. Multi-plane fields are planes
+ *   of N floats one after another:
+ *     D x, y1, y2 : [vertical, horizontal]                          2 planes
+ *     L y, w1, w2 : [ud_v, ud_h, lr_v, lr_h, c_v, c_h]              6 planes
+ *   where ud is the (i+1/2, j) grid, lr the (i, j+1/2) grid and c the pixel
+ *   grid of Condat's interpolation operators (Sec. II-D).
+ * Pointers. Every array argument is a DEVICE pointer (hipMalloc'ed or a
+ *   torch CUDA tensor on the current device) owned by the caller, unless the
+ *   argument says "host". The library never allocates or frees device memory:
+ *   scratch lives in a caller-provided workspace sized by the matching
+ *   *_workspace_size call. Outputs must not alias inputs or the workspace.
+ * Streams. `stream` is a hipStream_t passed as void* (NULL = the null
+ *   stream). Work is enqueued on it; calls that return scalars to the host
+ *   (tau, r, the geo_result) synchronise that stream before returning.
+ * Precision. Iterates are FP32, arithmetic FP32, the global quantities (the
+ *   l2-ball distance, the l1-ball thresholds, the stopping norms) FP64.
+ * Errors. 0 = success; positive = warning (GEO_MAXITER); negative = error.
+ *   On an error nothing is guaranteed about the outputs. No call throws.
+ *   Calls are thread-safe and reentrant as long as concurrent calls use
+ *   distinct workspaces and outputs.
+ */
+#ifndef GEOSSTV_H
+#define GEOSSTV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    GEO_OK = 0,
+    GEO_MAXITER = 1,        /* warning: iteration cap reached before tol   */
+    GEO_EINVAL = -1,        /* bad dims, params, sizes or null pointers    */
+    GEO_EWORKSPACE = -2,    /* workspace missing, too small or misaligned  */
+    GEO_EHIP = -3,          /* a HIP runtime call failed                   */
+    GEO_ENONFINITE = -4     /* NaN or Inf appeared in the iterates          */
+};
+
+/* Storage type of the dual variables y1..y4 inside the workspace. */
+enum { GEO_STORE_F32 = 0, GEO_STORE_BF16 = 1 };
+
+typedef struct {
+    int32_t n1, n2, n3; /* each >= 1; N = n1*n2*n3 < 2^31 */
+} geo_dims;
+
+/* Parameters of problem (15) and of the loop of Alg. 1. The step sizes are
+ * not parameters: they are the constants printed after eq. (24)
+ * (u 1/13, w1 1/4, w2 1/4, s 1, t 1/3, y1..y4 1/5). */
+typedef struct {
+    double eps;          /* radius of the fidelity ball (18), >= 0          */
+    double alpha;        /* radius of the sparse-noise l1 ball (16), >= 0   */
+    double beta;         /* radius of the stripe-noise l1 ball (17), >= 0   */
+    double mu_lo, mu_hi; /* box (19), mu_lo < mu_hi                         */
+    double omega;        /* GeoSSTV balance of eq. (13), >= 0               */
+    int32_t max_iter;    /* iteration cap, >= 1 (geo_solve)                 */
+    double tol;          /* stop after the first iteration with
+                            ||u+ - u||_2 / ||u||_2 < tol (eq. (28));
+                            tol <= 0 runs exactly max_iter iterations      */
+    int32_t dual_storage;/* GEO_STORE_F32 or GEO_STORE_BF16                 */
+    int32_t check_every; /* iterations between host checks of the stopping
+                            flag (0 = 32); the count returned is exact
+                            whatever this is, since the device stops
+                            iterating on its own once the rule is met      */
+} geo_params;
+
+typedef struct {
+    int32_t iters;       /* iterations performed by this call               */
+    int32_t converged;   /* 1 if the stopping rule was met                  */
+    double rel_change;   /* ||u+ - u|| / ||u|| of the last iteration         */
+    double r;            /* ||y4'/gamma - v||_2 of the last iteration        */
+    double tau_s, tau_t; /* soft-threshold levels of the last l1 projections
+                            (0 inside the ball, +inf for a zero radius)     */
+    int32_t total_iters; /* iterations since geo_state_init                  */
+    int32_t fallback_passes; /* extra threshold passes of the last call     */
+} geo_result;
+
+/* Workspace of a solver state for one cube (bytes, 256-byte aligned base
+ * required). Errors: GEO_EINVAL for bad dims/params. */
+int geo_workspace_size(geo_dims dims, const geo_params *p, size_t *bytes);
+
+/* Set the state of Alg. 1 to its initial point: u = v, every other
+ * variable zero (the paper leaves the initial point open; this is the
+ * reading used). v: N floats. */
+int geo_state_init(geo_dims dims, const geo_params *p, const float *v,
+                   void *ws, size_t ws_bytes, void *stream);
+
+/* Run up to n_iter iterations of Alg. 1 (steps 1-15) on the state in ws,
+ * stopping early by the rule of eq. (28) when p->tol > 0. v must be the cube
+ * the state was initialised with. Blocking: fills *out (may be NULL).
+ * Returns GEO_OK, GEO_MAXITER (tol > 0 and not met) or an error. */
+int geo_step(geo_dims dims, const geo_params *p, const float *v,
+             void *ws, size_t ws_bytes, int32_t n_iter, void *stream,
+             geo_result *out);
+
+/* geo_step with HIP events recorded at the phase boundaries of every
+ * iteration on `stream` (instrumentation for benchmarks; the events add a
+ * few microseconds per iteration). phase_ms (host, GEO_NPHASE doubles)
+ * receives the summed GPU time of each phase over the call:
+ *   0 sweep A  (steps 1, 4, 5, 11, 12 and the u' part of 14 fused)
+ *   1 the exact soft-threshold search of the two l1-ball projections
+ *   2 sweep B  (steps 2, 3, 13 and the rest of 14)
+ *   3 finalize (the l2-ball factor of step 15 and the stopping rule) */
+#define GEO_NPHASE 4
+int geo_step_profiled(geo_dims dims, const geo_params *p, const float *v,
+                      void *ws, size_t ws_bytes, int32_t n_iter, void *stream,
+                      geo_result *out, double *phase_ms);
+
+/* geo_state_init + geo_step(max_iter) + copy of u, s, t (N floats each). */
+int geo_solve(geo_dims dims, const geo_params *p, const float *v,
+              float *u, float *s, float *t, void *ws, size_t ws_bytes,
+              void *stream, geo_result *out);
+
+/* State variables, for parity tests, checkpointing and resume. */
+enum {
+    GEO_VAR_U = 0, GEO_VAR_S, GEO_VAR_T, GEO_VAR_W1, GEO_VAR_W2,
+    GEO_VAR_Y1, GEO_VAR_Y2, GEO_VAR_Y3, GEO_VAR_Y4
+};
+
+/* Copy a state variable out of / into the workspace in FP32 (planes as
+ * above: 1 for u, s, t, y3, y4; 6 for w1, w2; 2 for y1, y2). p gives the
+ * storage type of the workspace. Loading any state is allowed, including
+ * entries the operators never read. v is needed to read y4 (the workspace
+ * keeps y4 in a scaled form). Asynchronous. */
+int geo_state_get(geo_dims dims, const geo_params *p, const void *ws, size_t ws_bytes,
+                  int32_t var, const float *v, float *out, void *stream);
+int geo_state_set(geo_dims dims, const geo_params *p, void *ws, size_t ws_bytes,
+                  int32_t var, const float *v, const float *in, void *stream);
+
+/* Linear operators of problem (20) (Sec. II-A differences with the Neumann
+ * boundary; Condat's interpolation operators of Sec. II-D in the reading
+ * where dual edge fields live on interior edges only). Asynchronous.
+ *   op               forward            planes in -> out
+ *   GEO_OP_DV        D_v (along i)       1 -> 1
+ *   GEO_OP_DH        D_h (along j)       1 -> 1
+ *   GEO_OP_DS        D_s (along k)       1 -> 1
+ *   GEO_OP_D         (D_v; D_h)          1 -> 2
+ *   GEO_OP_DDS       D D_s               1 -> 2
+ *   GEO_OP_L_UD      L_ud                2 -> 2
+ *   GEO_OP_L_LR      L_lr                2 -> 2
+ *   GEO_OP_L_C       L_c                 2 -> 2
+ *   GEO_OP_L         (L_ud; L_lr; L_c)   2 -> 6
+ *   GEO_OP_K         stacked operator of (20): (u,s,t,w1,w2) 15 -> 6 (y1..y4)
+ * adjoint != 0 applies the transpose (planes out -> in). */
+enum {
+    GEO_OP_DV = 0, GEO_OP_DH, GEO_OP_DS, GEO_OP_D, GEO_OP_DDS,
+    GEO_OP_L_UD, GEO_OP_L_LR, GEO_OP_L_C, GEO_OP_L, GEO_OP_K
+};
+int geo_apply_op(int32_t op, int32_t adjoint, geo_dims dims, const float *in,
+                 float *out, void *stream);
+
+/* Projection onto {z : ||z||_1 <= radius} (constraints (16), (17); exact:
+ * soft threshold at the tau with sum max(|x|-tau, 0) = radius, found by a
+ * deterministic radix search over the FP32 bit patterns with exact integer
+ * bin sums). x, out: n floats (may alias). *tau (host) receives the level
+ * (0 inside the ball, +inf for radius 0). Blocking. */
+int geo_project_l1_workspace_size(int64_t n, size_t *bytes);
+int geo_project_l1(const float *x, int64_t n, double radius, float *out,
+                   double *tau, void *ws, size_t ws_bytes, void *stream);
+
+/* Projection onto the ball of radius eps around center, eq. (23). *r (host)
+ * receives ||x - center||_2 (FP64). Blocking. */
+int geo_project_l2_workspace_size(int64_t n, size_t *bytes);
+int geo_project_l2(const float *x, const float *center, int64_t n, double eps,
+                   float *out, double *r, void *ws, size_t ws_bytes, void *stream);
+
+/* Prox of gamma ||.||_{1,2}, eq. (24), on groups (xa[q], xb[q]). */
+int geo_prox_l12(const float *xa, const float *xb, int64_t n, double gamma,
+                 float *oa, float *ob, void *stream);
+
+/* Box projection, eq. (21). */
+int geo_project_box(const float *x, int64_t n, double lo, double hi, float *out,
+                    void *stream);
+
+const char *geo_strerror(int status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GEOSSTV_H */

@@ -1,0 +1,262 @@
+"""GeoSSTV hyperspectral denoising and destriping on AMD MI355X (gfx950).
+
+Python binding of the C ABI in ``include/geosstv.h`` (library
+``libgeosstv.so`` next to this file). The functions carry the C names and
+only marshal arguments: torch tensors on the GPU become device pointers, the
+current torch stream becomes the HIP stream. Every step of the solver runs in
+the library's HIP kernels; there is no Python or CPU fallback, and importing
+any entry point without the built library raises.
+
+Cube layout: band-sequential float32 tensors of shape (N3, N1, N2), i.e.
+element (i, j, k) of the paper's N1 x N2 x N3 cube at [k, i, j].
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+__all__ = [
+    "geo_dims", "geo_params", "geo_result", "GeoError", "lib", "library_path",
+    "geo_workspace_size", "geo_state_init", "geo_step", "geo_step_profiled", "geo_solve", "geo_state_get",
+    "geo_state_set", "geo_apply_op", "geo_project_l1", "geo_project_l2", "geo_prox_l12",
+    "geo_project_box", "geo_strerror", "OPS", "VARS", "VAR_PLANES", "Workspace",
+]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "libgeosstv.so")
+
+GEO_OK, GEO_MAXITER = 0, 1
+GEO_STORE_F32, GEO_STORE_BF16 = 0, 1
+OPS = dict(dv=0, dh=1, ds=2, d=3, dds=4, l_ud=5, l_lr=6, l_c=7, l=8, k=9)
+OP_PLANES = dict(dv=(1, 1), dh=(1, 1), ds=(1, 1), d=(1, 2), dds=(1, 2), l_ud=(2, 2),
+                 l_lr=(2, 2), l_c=(2, 2), l=(2, 6), k=(15, 6))
+VARS = dict(u=0, s=1, t=2, w1=3, w2=4, y1=5, y2=6, y3=7, y4=8)
+VAR_PLANES = dict(u=1, s=1, t=1, w1=6, w2=6, y1=2, y2=2, y3=1, y4=1)
+
+
+class geo_dims(ctypes.Structure):
+    _fields_ = [("n1", ctypes.c_int32), ("n2", ctypes.c_int32), ("n3", ctypes.c_int32)]
+
+
+class geo_params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
+                ("mu_lo", ctypes.c_double), ("mu_hi", ctypes.c_double),
+                ("omega", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("tol", ctypes.c_double), ("dual_storage", ctypes.c_int32),
+                ("check_every", ctypes.c_int32)]
+
+
+class geo_result(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("rel_change", ctypes.c_double), ("r", ctypes.c_double),
+                ("tau_s", ctypes.c_double), ("tau_t", ctypes.c_double),
+                ("total_iters", ctypes.c_int32), ("fallback_passes", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class GeoError(RuntimeError):
+    def __init__(self, status, where):
+        super().__init__(f"{where}: {geo_strerror(status)} (status {status})")
+        self.status = status
+
+
+_lib = None
+_vp, _sz = ctypes.c_void_p, ctypes.c_size_t
+
+
+def lib():
+    """The loaded library; raises if it was not built (no fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise ImportError(f"{library_path} is missing: build it with "
+                              "`python paper_2510_00562_amd/build.py`")
+        L = ctypes.CDLL(library_path)
+        i32, i64, d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+        P, R = ctypes.POINTER(geo_params), ctypes.POINTER(geo_result)
+        sig = {
+            "geo_workspace_size": [geo_dims, P, ctypes.POINTER(_sz)],
+            "geo_state_init": [geo_dims, P, _vp, _vp, _sz, _vp],
+            "geo_step": [geo_dims, P, _vp, _vp, _sz, i32, _vp, R],
+            "geo_solve": [geo_dims, P, _vp, _vp, _vp, _vp, _vp, _sz, _vp, R],
+            "geo_step_profiled": [geo_dims, P, _vp, _vp, _sz, i32, _vp, R,
+                                  ctypes.POINTER(ctypes.c_double)],
+            "geo_state_get": [geo_dims, P, _vp, _sz, i32, _vp, _vp, _vp],
+            "geo_state_set": [geo_dims, P, _vp, _sz, i32, _vp, _vp, _vp],
+            "geo_apply_op": [i32, i32, geo_dims, _vp, _vp, _vp],
+            "geo_project_l1_workspace_size": [i64, ctypes.POINTER(_sz)],
+            "geo_project_l1": [_vp, i64, d, _vp, ctypes.POINTER(d), _vp, _sz, _vp],
+            "geo_project_l2_workspace_size": [i64, ctypes.POINTER(_sz)],
+            "geo_project_l2": [_vp, _vp, i64, d, _vp, ctypes.POINTER(d), _vp, _sz, _vp],
+            "geo_prox_l12": [_vp, _vp, i64, d, _vp, _vp, _vp],
+            "geo_project_box": [_vp, i64, d, d, _vp, _vp],
+            "geo_strerror": [ctypes.c_int],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_char_p if name == "geo_strerror" else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def geo_strerror(status: int) -> str:
+    return lib().geo_strerror(status).decode()
+
+
+# ---------------------------------------------------------------- marshalling
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    torch = _torch()
+    if not t.is_cuda:
+        raise ValueError("expected a GPU tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected dtype {dtype}, got {t.dtype}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _f32(t):
+    return _ptr(t, _torch().float32)
+
+
+def _stream(stream=None):
+    torch = _torch()
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def dims_of(shape) -> geo_dims:
+    """geo_dims from a BSQ shape (N3, N1, N2) (a leading plane axis allowed)."""
+    n3, n1, n2 = shape[-3:]
+    return geo_dims(n1, n2, n3)
+
+
+def params(eps, alpha, beta, mu_lo=0.0, mu_hi=1.0, omega=0.03, max_iter=1000, tol=0.0,
+           dual_storage=GEO_STORE_F32, check_every=0) -> geo_params:
+    return geo_params(eps, alpha, beta, mu_lo, mu_hi, omega, max_iter, tol, dual_storage,
+                      check_every)
+
+
+def _check(rc, where, allow_maxiter=False):
+    if rc < 0 or (rc > 0 and not allow_maxiter):
+        raise GeoError(rc, where)
+    return rc
+
+
+# ---------------------------------------------------------------- entry points
+def geo_workspace_size(dims: geo_dims, p: geo_params | None = None) -> int:
+    n = _sz()
+    _check(lib().geo_workspace_size(dims, ctypes.byref(p) if p is not None else None,
+                                    ctypes.byref(n)), "geo_workspace_size")
+    return n.value
+
+
+class Workspace:
+    """A device buffer of the size the library asks for (torch allocates it;
+    256-byte alignment is guaranteed by the caching allocator)."""
+
+    def __init__(self, nbytes: int, device="cuda"):
+        torch = _torch()
+        self.tensor = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+        self.nbytes = int(nbytes)
+        assert self.tensor.data_ptr() % 256 == 0
+
+    @property
+    def ptr(self):
+        return ctypes.c_void_p(self.tensor.data_ptr())
+
+
+def geo_state_init(dims, p, v, ws: Workspace, stream=None):
+    _check(lib().geo_state_init(dims, ctypes.byref(p), _f32(v), ws.ptr, ws.nbytes,
+                                _stream(stream)), "geo_state_init")
+
+
+def geo_step(dims, p, v, ws: Workspace, n_iter: int, stream=None) -> geo_result:
+    out = geo_result()
+    _check(lib().geo_step(dims, ctypes.byref(p), _f32(v), ws.ptr, ws.nbytes, int(n_iter),
+                          _stream(stream), ctypes.byref(out)), "geo_step", allow_maxiter=True)
+    return out
+
+
+PHASES = ("sweep_a", "l1_select", "sweep_b", "finalize")
+
+
+def geo_step_profiled(dims, p, v, ws: Workspace, n_iter: int, stream=None):
+    """geo_step with per-phase GPU times (HIP events): returns
+    (geo_result, {phase: summed milliseconds})."""
+    out = geo_result()
+    ms = (ctypes.c_double * len(PHASES))()
+    _check(lib().geo_step_profiled(dims, ctypes.byref(p), _f32(v), ws.ptr, ws.nbytes, int(n_iter),
+                                   _stream(stream), ctypes.byref(out), ms),
+           "geo_step_profiled", allow_maxiter=True)
+    return out, dict(zip(PHASES, list(ms)))
+
+
+def geo_solve(dims, p, v, u, s, t, ws: Workspace, stream=None) -> geo_result:
+    out = geo_result()
+    _check(lib().geo_solve(dims, ctypes.byref(p), _f32(v), _f32(u), _f32(s), _f32(t), ws.ptr,
+                           ws.nbytes, _stream(stream), ctypes.byref(out)), "geo_solve",
+           allow_maxiter=True)
+    return out
+
+
+def geo_state_get(dims, p, ws: Workspace, var: str, v, out, stream=None):
+    _check(lib().geo_state_get(dims, ctypes.byref(p), ws.ptr, ws.nbytes, VARS[var], _f32(v),
+                               _f32(out), _stream(stream)), "geo_state_get")
+    return out
+
+
+def geo_state_set(dims, p, ws: Workspace, var: str, v, x, stream=None):
+    _check(lib().geo_state_set(dims, ctypes.byref(p), ws.ptr, ws.nbytes, VARS[var], _f32(v),
+                               _f32(x), _stream(stream)), "geo_state_set")
+
+
+def geo_apply_op(op: str, adjoint: bool, dims, x, out, stream=None):
+    _check(lib().geo_apply_op(OPS[op], 1 if adjoint else 0, dims, _f32(x), _f32(out),
+                              _stream(stream)), "geo_apply_op")
+    return out
+
+
+def geo_project_l1(x, radius: float, out, ws: Workspace | None = None, stream=None) -> float:
+    n = x.numel()
+    if ws is None:
+        need = _sz()
+        _check(lib().geo_project_l1_workspace_size(n, ctypes.byref(need)), "workspace")
+        ws = Workspace(need.value, device=x.device)
+    tau = ctypes.c_double()
+    _check(lib().geo_project_l1(_f32(x), n, float(radius), _f32(out), ctypes.byref(tau), ws.ptr,
+                                ws.nbytes, _stream(stream)), "geo_project_l1")
+    return tau.value
+
+
+def geo_project_l2(x, center, eps: float, out, ws: Workspace | None = None, stream=None) -> float:
+    n = x.numel()
+    if ws is None:
+        need = _sz()
+        _check(lib().geo_project_l2_workspace_size(n, ctypes.byref(need)), "workspace")
+        ws = Workspace(need.value, device=x.device)
+    r = ctypes.c_double()
+    _check(lib().geo_project_l2(_f32(x), _f32(center), n, float(eps), _f32(out), ctypes.byref(r),
+                                ws.ptr, ws.nbytes, _stream(stream)), "geo_project_l2")
+    return r.value
+
+
+def geo_prox_l12(xa, xb, gamma: float, oa, ob, stream=None):
+    _check(lib().geo_prox_l12(_f32(xa), _f32(xb), xa.numel(), float(gamma), _f32(oa), _f32(ob),
+                              _stream(stream)), "geo_prox_l12")
+
+
+def geo_project_box(x, lo: float, hi: float, out, stream=None):
+    _check(lib().geo_project_box(_f32(x), x.numel(), float(lo), float(hi), _f32(out),
+                                 _stream(stream)), "geo_project_box")
+    return out

@@ -1,0 +1,352 @@
+// extern "C" entry points declared in include/geosstv.h: argument checks,
+// workspace carving and launch sequencing. No device memory is allocated
+// here; every buffer is the caller's.
+#include <math.h>
+#include <string.h>
+
+#include "solver.hpp"
+
+namespace geo {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(int n1, int n2, int n3, int dual_storage)
+{
+    Layout L;
+    memset(&L, 0, sizeof L);
+    const size_t N = (size_t)n1 * n2 * n3;
+    const size_t f4 = N * sizeof(float);
+    const int db = dual_storage == GEO_STORE_BF16 ? 2 : 4;
+    const size_t fd = N * db;
+    const SweepGrid g = sweep_grid(n1, n2, n3);
+    L.dual_bytes = db;
+    L.n_part = 2 * g.blocks() + point_blocks((int64_t)N);
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    L.scalars = take(sizeof(DevScalars));
+    L.partials = take(sizeof(double) * (size_t)L.n_part);
+    L.hist = take(2 * sizeof(Hist));
+    L.y4p = take(fd);
+    L.zs = take(f4);
+    L.zt = take(f4);
+    for (int p = 0; p < 2; ++p) {
+        L.u[p] = take(f4);
+        L.s[p] = take(f4);
+        L.t[p] = take(f4);
+        L.w1[p] = take(6 * f4);
+        L.w2[p] = take(6 * f4);
+        L.y1[p] = take(2 * fd);
+        L.y2[p] = take(2 * fd);
+        L.y3[p] = take(fd);
+        L.y4[p] = take(fd);
+    }
+    L.total = o;
+    return L;
+}
+
+}  // namespace geo
+
+using namespace geo;
+
+namespace {
+
+thread_local hipError_t g_last_hip = hipSuccess;
+
+int hip_status(hipError_t e)
+{
+    if (e == hipSuccess) return GEO_OK;
+    g_last_hip = e;
+    return GEO_EHIP;
+}
+
+bool dims_ok(geo_dims d)
+{
+    if (d.n1 < 1 || d.n2 < 1 || d.n3 < 1) return false;
+    const int64_t N = (int64_t)d.n1 * d.n2 * d.n3;
+    return N < ((int64_t)1 << 31);
+}
+
+bool finite_nonneg(double x) { return isfinite(x) && x >= 0.0; }
+
+bool params_ok(const geo_params *p)
+{
+    if (!p) return false;
+    if (!finite_nonneg(p->eps) || !finite_nonneg(p->alpha) || !finite_nonneg(p->beta)) return false;
+    if (!finite_nonneg(p->omega)) return false;
+    if (!isfinite(p->mu_lo) || !isfinite(p->mu_hi) || !(p->mu_lo < p->mu_hi)) return false;
+    if (isnan(p->tol)) return false;
+    if (p->dual_storage != GEO_STORE_F32 && p->dual_storage != GEO_STORE_BF16) return false;
+    if (p->check_every < 0) return false;
+    return true;
+}
+
+Dims to_dims(geo_dims d)
+{
+    Dims x;
+    x.n1 = d.n1;
+    x.n2 = d.n2;
+    x.n3 = d.n3;
+    x.plane = (int64_t)d.n1 * d.n2 * d.n3;
+    return x;
+}
+
+int check_ws(geo_dims d, const geo_params *p, const void *ws, size_t ws_bytes, Layout *L)
+{
+    *L = make_layout(d.n1, d.n2, d.n3, p ? p->dual_storage : GEO_STORE_F32);
+    if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < L->total) return GEO_EWORKSPACE;
+    return GEO_OK;
+}
+
+hipStream_t S(void *stream) { return (hipStream_t)stream; }
+
+int read_scalars(const void *ws, const Layout &L, DevScalars *out, hipStream_t st)
+{
+    hipError_t e = hipMemcpyAsync(out, (const char *)ws + L.scalars, sizeof(DevScalars),
+                                  hipMemcpyDeviceToHost, st);
+    if (e != hipSuccess) return hip_status(e);
+    return hip_status(hipStreamSynchronize(st));
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *geo_strerror(int status)
+{
+    switch (status) {
+    case GEO_OK: return "success";
+    case GEO_MAXITER: return "iteration cap reached before the stopping rule held";
+    case GEO_EINVAL: return "invalid argument (dims, parameters, sizes or null pointer)";
+    case GEO_EWORKSPACE: return "workspace missing, misaligned (256 B) or too small";
+    case GEO_EHIP: return hipGetErrorString(g_last_hip);
+    case GEO_ENONFINITE: return "NaN or Inf appeared in the iterates";
+    default: return "unknown status";
+    }
+}
+
+int geo_workspace_size(geo_dims dims, const geo_params *p, size_t *bytes)
+{
+    if (!dims_ok(dims) || !bytes) return GEO_EINVAL;
+    if (p && (p->dual_storage != GEO_STORE_F32 && p->dual_storage != GEO_STORE_BF16))
+        return GEO_EINVAL;
+    *bytes = make_layout(dims.n1, dims.n2, dims.n3, p ? p->dual_storage : GEO_STORE_F32).total;
+    return GEO_OK;
+}
+
+int geo_state_init(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
+                   void *stream)
+{
+    if (!dims_ok(dims) || !params_ok(p) || !v) return GEO_EINVAL;
+    Layout L;
+    int rc = check_ws(dims, p, ws, ws_bytes, &L);
+    if (rc) return rc;
+    return hip_status(launch_init(to_dims(dims), v, ws, L, p->eps, p->tol, S(stream)));
+}
+
+static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
+                     int32_t n_iter, void *stream, geo_result *out, double *phase_ms)
+{
+    if (!dims_ok(dims) || !params_ok(p) || !v || n_iter < 0) return GEO_EINVAL;
+    Layout L;
+    int rc = check_ws(dims, p, ws, ws_bytes, &L);
+    if (rc) return rc;
+    const hipStream_t st = S(stream);
+    const Dims d = to_dims(dims);
+    IterParams ip{p->omega, p->mu_lo, p->mu_hi, p->alpha, p->beta};
+    rc = hip_status(launch_begin_call(ws, L, p->tol, st));
+    if (rc) return rc;
+    const int every = p->check_every > 0 ? p->check_every : 32;
+    DevScalars sc;
+    int launched = 0;
+    hipEvent_t *ev = nullptr;
+    if (phase_ms) {
+        for (int q = 0; q < GEO_NPHASE; ++q) phase_ms[q] = 0.0;
+        ev = new hipEvent_t[5 * (size_t)(n_iter > 0 ? n_iter : 1)];
+        for (int q = 0; q < 5 * n_iter; ++q) {
+            rc = hip_status(hipEventCreate(&ev[q]));
+            if (rc) return rc;
+        }
+    }
+    while (launched < n_iter) {
+        const int batch = (p->tol > 0.0) ? (n_iter - launched < every ? n_iter - launched : every)
+                                         : n_iter - launched;
+        for (int q = 0; q < batch; ++q) {
+            rc = hip_status(launch_iteration(d, v, ws, L, ip, st, ev ? ev + 5 * (launched + q) : nullptr));
+            if (rc) return rc;
+        }
+        launched += batch;
+        if (p->tol > 0.0 && launched < n_iter) {
+            rc = read_scalars(ws, L, &sc, st);
+            if (rc) return rc;
+            if (sc.stop) break;
+        }
+    }
+    rc = read_scalars(ws, L, &sc, st);
+    if (ev) {
+        for (int q = 0; q < launched && !rc; ++q)
+            for (int ph = 0; ph < GEO_NPHASE && !rc; ++ph) {
+                float ms = 0.f;
+                rc = hip_status(hipEventElapsedTime(&ms, ev[5 * q + ph], ev[5 * q + ph + 1]));
+                phase_ms[ph] += ms;
+            }
+        for (int q = 0; q < 5 * n_iter; ++q) (void)hipEventDestroy(ev[q]);
+        delete[] ev;
+    }
+    if (rc) return rc;
+    if (out) {
+        out->iters = (int32_t)sc.calls_iter;
+        out->converged = (p->tol > 0.0 && sc.stop && !sc.nonfinite) ? 1 : 0;
+        out->rel_change = sc.rel;
+        out->r = sc.r;
+        out->tau_s = sc.sel[0].tau;
+        out->tau_t = sc.sel[1].tau;
+        out->total_iters = (int32_t)sc.iter;
+        out->fallback_passes = (int32_t)sc.fallback;
+    }
+    if (sc.nonfinite) return GEO_ENONFINITE;
+    if (p->tol > 0.0 && !sc.stop) return GEO_MAXITER;
+    return GEO_OK;
+}
+
+int geo_step(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
+             int32_t n_iter, void *stream, geo_result *out)
+{
+    return step_impl(dims, p, v, ws, ws_bytes, n_iter, stream, out, nullptr);
+}
+
+int geo_step_profiled(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
+                      int32_t n_iter, void *stream, geo_result *out, double *phase_ms)
+{
+    if (!phase_ms) return GEO_EINVAL;
+    return step_impl(dims, p, v, ws, ws_bytes, n_iter, stream, out, phase_ms);
+}
+
+int geo_solve(geo_dims dims, const geo_params *p, const float *v, float *u, float *s, float *t,
+              void *ws, size_t ws_bytes, void *stream, geo_result *out)
+{
+    if (!params_ok(p) || p->max_iter < 1 || !u || !s || !t) return GEO_EINVAL;
+    int rc = geo_state_init(dims, p, v, ws, ws_bytes, stream);
+    if (rc) return rc;
+    const int step_rc = geo_step(dims, p, v, ws, ws_bytes, p->max_iter, stream, out);
+    if (step_rc < 0) return step_rc;
+    Layout L = make_layout(dims.n1, dims.n2, dims.n3, p->dual_storage);
+    const Dims d = to_dims(dims);
+    const hipStream_t st = S(stream);
+    rc = hip_status(launch_state_io(d, ws, L, GEO_VAR_U, v, u, nullptr, st));
+    if (!rc) rc = hip_status(launch_state_io(d, ws, L, GEO_VAR_S, v, s, nullptr, st));
+    if (!rc) rc = hip_status(launch_state_io(d, ws, L, GEO_VAR_T, v, t, nullptr, st));
+    if (!rc) rc = hip_status(hipStreamSynchronize(st));
+    return rc ? rc : step_rc;
+}
+
+static int state_io(geo_dims dims, const void *ws, size_t ws_bytes, int32_t var, const float *v,
+                    float *out, const float *in, int dual_storage, void *stream)
+{
+    if (!dims_ok(dims) || var < GEO_VAR_U || var > GEO_VAR_Y4) return GEO_EINVAL;
+    if (dual_storage != GEO_STORE_F32 && dual_storage != GEO_STORE_BF16) return GEO_EINVAL;
+    if ((out == nullptr) == (in == nullptr)) return GEO_EINVAL;
+    if (var == GEO_VAR_Y4 && !v && out) return GEO_EINVAL;
+    geo_params p;
+    memset(&p, 0, sizeof p);
+    p.dual_storage = dual_storage;
+    Layout L;
+    int rc = check_ws(dims, &p, ws, ws_bytes, &L);
+    if (rc) return rc;
+    return hip_status(launch_state_io(to_dims(dims), (void *)ws, L, var, v, out, in, S(stream)));
+}
+
+int geo_state_get(geo_dims dims, const geo_params *p, const void *ws, size_t ws_bytes, int32_t var,
+                  const float *v, float *out, void *stream)
+{
+    if (!out || !p) return GEO_EINVAL;
+    return state_io(dims, ws, ws_bytes, var, v, out, nullptr, p->dual_storage, stream);
+}
+
+int geo_state_set(geo_dims dims, const geo_params *p, void *ws, size_t ws_bytes, int32_t var,
+                  const float *v, const float *in, void *stream)
+{
+    if (!in || !p) return GEO_EINVAL;
+    return state_io(dims, ws, ws_bytes, var, v, nullptr, in, p->dual_storage, stream);
+}
+
+int geo_apply_op(int32_t op, int32_t adjoint, geo_dims dims, const float *in, float *out,
+                 void *stream)
+{
+    int pin, pout;
+    if (!dims_ok(dims) || !in || !out || op_planes(op, adjoint ? 1 : 0, &pin, &pout)) return GEO_EINVAL;
+    return hip_status(launch_apply_op(op, adjoint ? 1 : 0, to_dims(dims), in, out, S(stream)));
+}
+
+int geo_project_l1_workspace_size(int64_t n, size_t *bytes)
+{
+    if (n < 0 || !bytes) return GEO_EINVAL;
+    *bytes = align256(sizeof(SelState)) + sizeof(Hist);
+    return GEO_OK;
+}
+
+int geo_project_l1(const float *x, int64_t n, double radius, float *out, double *tau, void *ws,
+                   size_t ws_bytes, void *stream)
+{
+    if (n < 0 || !isfinite(radius) || radius < 0.0 || (n > 0 && (!x || !out))) return GEO_EINVAL;
+    size_t need;
+    geo_project_l1_workspace_size(n, &need);
+    if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < need) return GEO_EWORKSPACE;
+    const hipStream_t st = S(stream);
+    SelState *sel = (SelState *)ws;
+    Hist *hist = (Hist *)((char *)ws + align256(sizeof(SelState)));
+    int rc = hip_status(launch_l1_threshold(x, n, radius, sel, hist, st));
+    if (!rc && n > 0) rc = hip_status(launch_soft(x, n, sel, out, st));
+    SelState h;
+    if (!rc) rc = hip_status(hipMemcpyAsync(&h, sel, sizeof h, hipMemcpyDeviceToHost, st));
+    if (!rc) rc = hip_status(hipStreamSynchronize(st));
+    if (!rc && tau) *tau = h.tau;
+    return rc;
+}
+
+int geo_project_l2_workspace_size(int64_t n, size_t *bytes)
+{
+    if (n < 0 || !bytes) return GEO_EINVAL;
+    *bytes = align256(sizeof(double) * (size_t)l2_blocks(n > 0 ? n : 1)) + 256;
+    return GEO_OK;
+}
+
+int geo_project_l2(const float *x, const float *center, int64_t n, double eps, float *out, double *r,
+                   void *ws, size_t ws_bytes, void *stream)
+{
+    if (n < 1 || !x || !center || !out || !isfinite(eps) || eps < 0.0) return GEO_EINVAL;
+    size_t need;
+    geo_project_l2_workspace_size(n, &need);
+    if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < need) return GEO_EWORKSPACE;
+    const hipStream_t st = S(stream);
+    double *part = (double *)ws;
+    double *rd = (double *)((char *)ws + align256(sizeof(double) * (size_t)l2_blocks(n)));
+    int rc = hip_status(launch_l2(x, center, n, eps, out, part, rd, st));
+    double h = 0.0;
+    if (!rc) rc = hip_status(hipMemcpyAsync(&h, rd, sizeof h, hipMemcpyDeviceToHost, st));
+    if (!rc) rc = hip_status(hipStreamSynchronize(st));
+    if (!rc && r) *r = h;
+    return rc;
+}
+
+int geo_prox_l12(const float *xa, const float *xb, int64_t n, double gamma, float *oa, float *ob,
+                 void *stream)
+{
+    if (n < 0 || !isfinite(gamma) || gamma < 0.0) return GEO_EINVAL;
+    if (n == 0) return GEO_OK;
+    if (!xa || !xb || !oa || !ob) return GEO_EINVAL;
+    return hip_status(launch_prox_l12(xa, xb, n, (float)gamma, oa, ob, S(stream)));
+}
+
+int geo_project_box(const float *x, int64_t n, double lo, double hi, float *out, void *stream)
+{
+    if (n < 0 || !isfinite(lo) || !isfinite(hi) || !(lo < hi)) return GEO_EINVAL;
+    if (n == 0) return GEO_OK;
+    if (!x || !out) return GEO_EINVAL;
+    return hip_status(launch_box(x, n, (float)lo, (float)hi, out, S(stream)));
+}
+
+}  // extern "C"

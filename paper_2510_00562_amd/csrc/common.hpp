@@ -1,0 +1,86 @@
+// Device-side helpers shared by the gfx950 kernels of the GeoSSTV solver.
+//
+// Cube layout is band-sequential: element (i, j, k) of an N1 x N2 x N3 cube at
+// (k*N1 + i)*N2 + j, so a wavefront of 64 lanes along j reads 256 contiguous
+// bytes of one band row.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace geo {
+
+constexpr float kStepU = 1.0f / 13.0f;  // step sizes printed after eq. (24)
+constexpr float kStepW = 0.25f;         // w1 and w2
+constexpr float kStepT = 1.0f / 3.0f;
+constexpr float kStepY = 0.2f;          // y1..y4 (and s has step 1)
+
+// Storage of the dual variables: FP32, or BF16 with FP32 arithmetic.
+struct bf16 {
+    uint16_t bits;
+};
+
+__device__ __forceinline__ float ld(const float *p) { return *p; }
+__device__ __forceinline__ float ld(const bf16 *p)
+{
+    return __uint_as_float(((uint32_t)p->bits) << 16);
+}
+__device__ __forceinline__ void st(float *p, float x) { *p = x; }
+__device__ __forceinline__ void st(bf16 *p, float x)
+{
+    // round to nearest even; NaN stays NaN
+    uint32_t u = __float_as_uint(x);
+    uint32_t r = ((u & 0x7fffffffu) > 0x7f800000u) ? (u | 0x00400000u)
+                                                   : u + 0x7fffu + ((u >> 16) & 1u);
+    bf16 b;
+    b.bits = (uint16_t)(r >> 16);
+    *p = b;
+}
+
+struct Dims {
+    int n1, n2, n3;
+    int64_t plane;  // N = n1*n2*n3 (distance between planes of a field)
+};
+
+__device__ __forceinline__ int64_t vox(const Dims &d, int k, int i, int j)
+{
+    return ((int64_t)k * d.n1 + i) * d.n2 + j;
+}
+
+// Masks of the forward differences (Neumann boundary): an edge exists between
+// index x and x+1 only for x <= n-2.
+__device__ __forceinline__ float mask_le(int x, int n) { return (x >= 0 && x <= n - 2) ? 1.0f : 0.0f; }
+
+// Group shrink of eq. (24) on one pair, returning the shrunk pair.
+__device__ __forceinline__ void shrink2(float &a, float &b, float thr)
+{
+    float nr = sqrtf(a * a + b * b);
+    float f = nr > thr ? 1.0f - thr / nr : 0.0f;
+    a *= f;
+    b *= f;
+}
+
+// Wavefront-wide sum of a double (64 lanes).
+__device__ __forceinline__ double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Block-wide sum for blocks of up to 1024 threads; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double x, double *lds /* NT/64 */)
+{
+    x = wave_sum(x);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) lds[wid] = x;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) s += lds[w];
+    return s;
+}
+
+}  // namespace geo
