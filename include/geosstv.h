@@ -84,7 +84,10 @@ typedef struct {
     double tau_s, tau_t; /* soft-threshold levels of the last l1 projections
                             (0 inside the ball, +inf for a zero radius)     */
     int32_t total_iters; /* iterations since geo_state_init                  */
-    int32_t fallback_passes; /* extra threshold passes of the last call     */
+    int32_t fallback_passes; /* l1 thresholds found by the full search (the
+                                predicted window missed) during the call   */
+    int32_t cand_s, cand_t;  /* values inside the predicted windows in the
+                                last iteration (diagnostic)                */
 } geo_result;
 
 /* Workspace of a solver state for one cube (bytes, 256-byte aligned base

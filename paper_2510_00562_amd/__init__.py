@@ -50,7 +50,8 @@ class geo_result(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("rel_change", ctypes.c_double), ("r", ctypes.c_double),
                 ("tau_s", ctypes.c_double), ("tau_t", ctypes.c_double),
-                ("total_iters", ctypes.c_int32), ("fallback_passes", ctypes.c_int32)]
+                ("total_iters", ctypes.c_int32), ("fallback_passes", ctypes.c_int32),
+                ("cand_s", ctypes.c_int32), ("cand_t", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -73,6 +74,10 @@ def lib():
         if not os.path.exists(library_path):
             raise ImportError(f"{library_path} is missing: build it with "
                               "`python paper_2510_00562_amd/build.py`")
+        # torch ships its own HIP runtime with the same soname; load it first
+        # so that the library binds to it and the process holds one runtime
+        # (two HSA runtimes in one process do not share the device).
+        import torch  # noqa: F401
         L = ctypes.CDLL(library_path)
         i32, i64, d = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
         P, R = ctypes.POINTER(geo_params), ctypes.POINTER(geo_result)

@@ -18,9 +18,10 @@ Layout make_layout(int n1, int n2, int n3, int dual_storage)
     const size_t f4 = N * sizeof(float);
     const int db = dual_storage == GEO_STORE_BF16 ? 2 : 4;
     const size_t fd = N * db;
-    const SweepGrid g = sweep_grid(n1, n2, n3);
     L.dual_bytes = db;
-    L.n_part = 2 * g.blocks() + point_blocks((int64_t)N);
+    L.max_grid = sweep_a_max_grid(n1, n2, n3);
+    L.n_part = 2 * L.max_grid + sweep_b_blocks((int64_t)N);
+    L.cap = (int64_t)N / 16 > 65536 ? (int64_t)N / 16 : 65536;
     size_t o = 0;
     auto take = [&](size_t bytes) {
         size_t at = o;
@@ -31,8 +32,9 @@ Layout make_layout(int n1, int n2, int n3, int dual_storage)
     L.partials = take(sizeof(double) * (size_t)L.n_part);
     L.hist = take(2 * sizeof(Hist));
     L.y4p = take(fd);
-    L.zs = take(f4);
-    L.zt = take(f4);
+    L.winpart = take(sizeof(double) * 2 * 3 * (size_t)L.max_grid);
+    L.cand = take(sizeof(float) * 2 * (size_t)L.cap);
+    L.ccount = take(sizeof(uint32_t) * 2 * (size_t)L.max_grid);
     for (int p = 0; p < 2; ++p) {
         L.u[p] = take(f4);
         L.s[p] = take(f4);
@@ -144,7 +146,8 @@ int geo_state_init(geo_dims dims, const geo_params *p, const float *v, void *ws,
     Layout L;
     int rc = check_ws(dims, p, ws, ws_bytes, &L);
     if (rc) return rc;
-    return hip_status(launch_init(to_dims(dims), v, ws, L, p->eps, p->tol, S(stream)));
+    return hip_status(launch_init(to_dims(dims), v, ws, L, p->eps, p->tol, p->alpha, p->beta,
+                                  S(stream)));
 }
 
 static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
@@ -157,7 +160,7 @@ static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *w
     const hipStream_t st = S(stream);
     const Dims d = to_dims(dims);
     IterParams ip{p->omega, p->mu_lo, p->mu_hi, p->alpha, p->beta};
-    rc = hip_status(launch_begin_call(ws, L, p->tol, st));
+    rc = hip_status(launch_begin_call(ws, L, p->tol, p->alpha, p->beta, st));
     if (rc) return rc;
     const int every = p->check_every > 0 ? p->check_every : 32;
     DevScalars sc;
@@ -206,6 +209,8 @@ static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *w
         out->tau_t = sc.sel[1].tau;
         out->total_iters = (int32_t)sc.iter;
         out->fallback_passes = (int32_t)sc.fallback;
+        out->cand_s = (int32_t)sc.sel[0].cand_count;
+        out->cand_t = (int32_t)sc.sel[1].cand_count;
     }
     if (sc.nonfinite) return GEO_ENONFINITE;
     if (p->tol > 0.0 && !sc.stop) return GEO_MAXITER;

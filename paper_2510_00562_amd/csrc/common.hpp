@@ -37,6 +37,32 @@ __device__ __forceinline__ void st(bf16 *p, float x)
     *p = b;
 }
 
+// Pairs stored together: the (vertical, horizontal) components of a dual
+// edge field, or the two components of one l_{1,2} group of w.
+struct bf16x2 {
+    uint32_t bits;  // low half: first component, high half: second
+};
+template <typename DT> struct PairOf;
+template <> struct PairOf<float> { using type = float2; };
+template <> struct PairOf<bf16> { using type = bf16x2; };
+
+__device__ __forceinline__ float2 ld2(const float2 *p) { return *p; }
+__device__ __forceinline__ float2 ld2(const bf16x2 *p)
+{
+    const uint32_t b = p->bits;
+    return make_float2(__uint_as_float(b << 16), __uint_as_float(b & 0xffff0000u));
+}
+__device__ __forceinline__ void st2(float2 *p, float2 x) { *p = x; }
+__device__ __forceinline__ void st2(bf16x2 *p, float2 x)
+{
+    bf16 a, b;
+    st(&a, x.x);
+    st(&b, x.y);
+    bf16x2 o;
+    o.bits = (uint32_t)a.bits | ((uint32_t)b.bits << 16);
+    *p = o;
+}
+
 struct Dims {
     int n1, n2, n3;
     int64_t plane;  // N = n1*n2*n3 (distance between planes of a field)
@@ -51,11 +77,13 @@ __device__ __forceinline__ int64_t vox(const Dims &d, int k, int i, int j)
 // index x and x+1 only for x <= n-2.
 __device__ __forceinline__ float mask_le(int x, int n) { return (x >= 0 && x <= n - 2) ? 1.0f : 0.0f; }
 
-// Group shrink of eq. (24) on one pair, returning the shrunk pair.
+// Group shrink of eq. (24) on one pair: scale by max(1 - thr/||(a, b)||, 0),
+// with the reciprocal square root instruction (about 1 ulp); a zero pair
+// gives rsq = +inf and a zero scale.
 __device__ __forceinline__ void shrink2(float &a, float &b, float thr)
 {
-    float nr = sqrtf(a * a + b * b);
-    float f = nr > thr ? 1.0f - thr / nr : 0.0f;
+    const float r = __builtin_amdgcn_rsqf(a * a + b * b);
+    const float f = fmaxf(1.0f - thr * r, 0.0f);
     a *= f;
     b *= f;
 }
@@ -81,6 +109,25 @@ __device__ __forceinline__ double block_sum(double x, double *lds /* NT/64 */)
     if (threadIdx.x == 0)
         for (int w = 0; w < NT / 64; ++w) s += lds[w];
     return s;
+}
+
+}  // namespace geo
+
+namespace geo {
+
+// The inputs of the two l1-ball projections (steps 2 and 3 of Alg. 1) and the
+// lazily scaled y4, written with explicit rounding operations so that every
+// kernel that evaluates them (both sweeps and the fallback threshold search)
+// gets bit-identical values.
+__device__ __forceinline__ float y4_of(float y4s, float v, float c4, float d4v)
+{
+    return __fmul_rn(c4, __fsub_rn(y4s, __fmul_rn(d4v, v)));
+}
+__device__ __forceinline__ float zs_of(float s, float y4) { return __fsub_rn(s, y4); }
+// y3m = y3 at (i-1) (0 on the first row), y3c = y3 at i masked by m_v(i)
+__device__ __forceinline__ float zt_of(float t, float y3m, float y3c, float y4)
+{
+    return __fsub_rn(t, __fmul_rn(kStepT, __fadd_rn(__fsub_rn(y3m, y3c), y4)));
 }
 
 }  // namespace geo

@@ -34,10 +34,6 @@ __device__ __forceinline__ uint64_t significand(uint32_t p)
 __device__ __forceinline__ int lvl_shift(int level) { return level == 0 ? 20 : (level == 1 ? 10 : 0); }
 __device__ __forceinline__ int lvl_bins(int level) { return level == 0 ? 2048 : 1024; }
 
-struct ZPtrs {
-    const float *z[2];
-};
-
 __global__ __launch_bounds__(kSelThreads) void k_select_begin(SelState *sel, int nfields, double r0,
                                                               double r1, Hist *hist,
                                                               const uint32_t *stop)
@@ -56,16 +52,55 @@ __global__ __launch_bounds__(kSelThreads) void k_select_begin(SelState *sel, int
         s.c_above = 0ull;
         s.prefix = 0u;
         s.level = 0u;
-        s.pad = 0u;
         s.done = s.radius <= 0.0 ? 1u : 0u;
         s.tau = s.radius <= 0.0 ? __longlong_as_double(0x7ff0000000000000ll) : 0.0;
+        s.tau_prev = 0.0;
+        s.tau_prev2 = 0.0;
+        s.full = 1u;
+        s.win_lo = s.win_hi = 0.f;
+        s.win_on = 0u;
+        s.cand_count = 0u;
         sel[f] = s;
     }
 }
 
+// Values of |z| come either from arrays (standalone projection) or are
+// evaluated from the solver state exactly as the sweeps evaluate them.
+struct ArraySrc {
+    const float *z[2];
+    __device__ __forceinline__ void begin() const {}
+    __device__ __forceinline__ float get(int f, int64_t q) const { return z[f][q]; }
+};
+
+template <typename DT>
+struct StateSrc {
+    ZState zs;
+    int par;
+    float c4, d4v;
+    __device__ __forceinline__ void begin()
+    {
+        par = (int)(zs.sc->iter & 1u);
+        c4 = (float)zs.sc->c4;
+        d4v = (float)(zs.sc->d4 * 0.2);
+    }
+    __device__ __forceinline__ float get(int f, int64_t q) const
+    {
+        const DT *y4 = (const DT *)zs.y4[par];
+        const float y = y4_of(ld(y4 + q), zs.v[q], c4, d4v);
+        if (f == 0) return zs_of(zs.s[par][q], y);
+        const DT *y3 = (const DT *)zs.y3[par];
+        const int n1 = zs.d.n1, n2 = zs.d.n2;
+        const int i = (int)((q / n2) % n1);
+        const float y3c = i <= n1 - 2 ? ld(y3 + q) : 0.f;
+        const float y3m = i >= 1 ? ld(y3 + q - n2) : 0.f;
+        return zt_of(zs.t[par][q], y3m, y3c, y);
+    }
+};
+
 // Histogram of the pattern bits of one radix level, restricted to values
 // whose higher bits equal the prefix chosen by the previous levels.
-__global__ __launch_bounds__(kSelThreads) void k_hist(ZPtrs zp, int64_t n, const SelState *sel,
+template <typename Src>
+__global__ __launch_bounds__(kSelThreads) void k_hist(Src src, int64_t n, const SelState *sel,
                                                       Hist *hist, int level, const uint32_t *stop)
 {
     if (stop && *stop) return;
@@ -79,12 +114,12 @@ __global__ __launch_bounds__(kSelThreads) void k_hist(ZPtrs zp, int64_t n, const
         ms[b] = 0ull;
     }
     __syncthreads();
+    src.begin();
     const uint32_t prefix = sel[f].prefix;
     const int pshift = shift + (level == 0 ? 11 : 10);
-    const float *z = zp.z[f];
     const int64_t stride = (int64_t)gridDim.x * kSelThreads;
     for (int64_t q = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; q < n; q += stride) {
-        uint32_t p = abs_bits(z[q]);
+        uint32_t p = abs_bits(src.get(f, q));
         if (level > 0 && (p >> pshift) != prefix) continue;
         uint32_t b = (p >> shift) & (uint32_t)(bins - 1);
         atomicAdd(&cnt[b], 1u);
@@ -97,6 +132,35 @@ __global__ __launch_bounds__(kSelThreads) void k_hist(ZPtrs zp, int64_t n, const
             atomicAdd((unsigned long long *)&hist[f].msum[b], ms[b]);
         }
     }
+}
+
+// Window for the next iteration: tau is extrapolated linearly from the last
+// two levels, and the half-width is three times the error the same
+// extrapolation made for this iteration (plus 2e-4 tau, and never less than
+// the last step when the history is short or the prediction failed).
+__device__ void set_window(SelState &o, bool missed)
+{
+    const double tau = o.tau;
+    if (!(tau > 0.0) || !isfinite(tau)) {
+        o.win_on = 0u;
+        o.tau_prev2 = 0.0;
+        o.tau_prev = tau;
+        return;
+    }
+    const double t1 = o.tau_prev, t2 = o.tau_prev2;
+    const bool h1 = t1 > 0.0 && isfinite(t1), h2 = h1 && t2 > 0.0 && isfinite(t2);
+    const double step = h1 ? tau - t1 : 0.05 * tau;
+    const double err = h2 ? fabs(tau - (2.0 * t1 - t2)) : fabs(step);
+    double h = 3.0 * err + 2e-4 * tau;
+    if (!h2 || missed) h = fmax(h, fabs(step) + 2e-4 * tau);
+    const double c = tau + (h1 ? step : 0.0);
+    double lo = c - h, hi = c + h;
+    if (lo < 0.0) lo = 0.0;
+    o.win_lo = __double2float_rd(lo);
+    o.win_hi = __double2float_ru(hi);
+    o.win_on = 1u;
+    o.tau_prev2 = h1 ? t1 : 0.0;
+    o.tau_prev = tau;
 }
 
 // One block per field: pick the bin that holds tau, or finish.
@@ -175,7 +239,8 @@ __global__ __launch_bounds__(kSelThreads) void k_select_level(SelState *sel, His
         if (mine >= 0) atomicMax(&best, mine);
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
+    __shared__ uint32_t fin;
+    if (threadIdx.x == 0) {
     int b = best;
     // Below level 0 the lowest edge of the range has f > radius by
     // construction; FP64 rounding of a differently ordered sum must not turn
@@ -228,20 +293,271 @@ __global__ __launch_bounds__(kSelThreads) void k_select_level(SelState *sel, His
             o.level = (uint32_t)(level + 1);
         }
     }
+    if (o.done) set_window(o, true);
     sel[f] = o;
+    fin = o.done;
+    }
+    __syncthreads();
+    // the next level accumulates into a clean histogram
+    if (!fin)
+        for (int q = threadIdx.x; q < kHistBins; q += kSelThreads) {
+            hist[f].count[q] = 0u;
+            hist[f].msum[q] = 0ull;
+        }
 }
 
-__global__ __launch_bounds__(kSelThreads) void k_hist_clear(Hist *hist, int nfields,
-                                                            const SelState *sel,
-                                                            const uint32_t *stop)
+// Threshold search over the candidates of the predicted window (one block
+// per field). The window holds tau exactly when f(hi) <= radius <= f(lo),
+// f(x) = sum max(|z| - x, 0), with f(hi) = S_above - hi C_above and
+// f(lo) = f(hi) + sum over candidates of (a - lo) + (hi - lo) C_above.
+// Then a radix search over the candidates' bit patterns (levels of at most
+// 11 bits aligned to multiples of their width, so no bin straddles an
+// exponent and the bin sums stay exact integers) finds tau. Otherwise the
+// block prepares the full radix search (level 0) on the whole field.
+constexpr int kWinThreads = 1024;
+constexpr int kWinBins = 1024;
+
+// Block-wide exclusive prefix sum (kWinThreads threads, fixed order, so the
+// FP64 results are deterministic). wsum: kWinThreads/64 entries of LDS.
+template <typename T>
+__device__ __forceinline__ T block_exclusive_scan(T x, T *wsum, T &total)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    T inc = x;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const T y = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += y;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    T before = T(0), all = T(0);
+    for (int q = 0; q < kWinThreads / 64; ++q) {
+        const T v = wsum[q];
+        if (q < w) before += v;
+        all += v;
+    }
+    __syncthreads();
+    total = all;
+    return before + inc - x;
+}
+
+__device__ __forceinline__ double bin_value(unsigned long long msum, uint32_t first_pattern)
+{
+    const uint32_t e = first_pattern >> 23;
+    return (double)msum * ldexp(1.0, (int)(e ? e : 1u) - 150);
+}
+
+__global__ __launch_bounds__(kWinThreads) void k_select_window(SelState *sel, Hist *hist,
+                                                               const double *winpart, int grid_a,
+                                                               const float *cand,
+                                                               const uint32_t *ccount, int capb,
+                                                               const uint32_t *stop,
+                                                               uint32_t *fallback_counter)
 {
     if (stop && *stop) return;
     const int f = blockIdx.x;
-    if (f >= nfields || sel[f].done) return;
-    for (int b = threadIdx.x; b < kHistBins; b += kSelThreads) {
-        hist[f].count[b] = 0u;
-        hist[f].msum[b] = 0ull;
+    __shared__ SelState s;
+    __shared__ uint32_t cnt[kWinBins];
+    __shared__ unsigned long long ms[kWinBins];
+    __shared__ uint32_t pre[kMaxSweepGrid];
+    __shared__ double wsd[kWinThreads / 64];
+    __shared__ uint32_t wsu[kWinThreads / 64];
+    __shared__ double tot[3];
+    __shared__ int verdict;  // 0 searching, 1 done, 2 full search needed
+    __shared__ int best;
+    __shared__ uint32_t ovf, ctot;
+    __shared__ uint32_t nbase;
+    __shared__ int nshift, nnb;
+    __shared__ double nS, nC;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        s = sel[f];
+        ovf = 0u;
+        verdict = 0;
     }
+    __syncthreads();
+    if (s.radius <= 0.0) {  // zero radius: the ball is {0}
+        if (tid == 0) {
+            SelState o = s;
+            o.tau = __longlong_as_double(0x7ff0000000000000ll);
+            o.done = 1u;
+            o.full = 0u;
+            o.cand_count = 0u;
+            o.win_on = 0u;
+            sel[f] = o;
+        }
+        return;
+    }
+    // block partials of sweep A (fixed order) and the candidate slices
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    uint32_t mine = 0u;  // this thread's slice counts (grid_a <= 2 * kWinThreads)
+    for (int b = tid; b < grid_a; b += kWinThreads) {
+        const double *w = winpart + ((int64_t)f * grid_a + b) * 3;
+        a0 += w[0];
+        a1 += w[1];
+        a2 += w[2];
+    }
+    for (int b = 2 * tid; b < 2 * tid + 2 && b < grid_a; ++b) {
+        uint32_t cb = ccount[(int64_t)f * grid_a + b];
+        if (cb > (uint32_t)capb) {
+            atomicOr(&ovf, 1u);
+            cb = (uint32_t)capb;
+        }
+        pre[b] = cb;
+        mine += cb;
+    }
+    uint32_t all_c;
+    const uint32_t off = block_exclusive_scan<uint32_t>(mine, wsu, all_c);
+    {
+        uint32_t acc = off;
+        for (int b = 2 * tid; b < 2 * tid + 2 && b < grid_a; ++b) {
+            const uint32_t cb = pre[b];
+            pre[b] = acc;
+            acc += cb;
+        }
+    }
+    double t0, t1, t2;
+    (void)block_exclusive_scan<double>(a0, wsd, t0);
+    (void)block_exclusive_scan<double>(a1, wsd, t1);
+    (void)block_exclusive_scan<double>(a2, wsd, t2);
+    if (tid == 0) {
+        ctot = all_c;
+        tot[0] = t0;
+        tot[1] = t1;
+        tot[2] = t2;
+        s.cand_count = all_c;
+        const double radius = s.radius;
+        if (t2 <= radius) {
+            verdict = 1;  // inside the ball
+            s.tau = 0.0;
+        } else if (!s.win_on || ovf || (double)s.win_hi * t0 < t1 - radius) {
+            verdict = 2;  // no window, overflow, or tau above the window
+        }
+    }
+    __syncthreads();
+    const uint32_t Pa = __float_as_uint(s.win_lo), Pb = __float_as_uint(s.win_hi);
+    uint32_t base = 0u;
+    int shift = 0, nb = 0;
+    double Sab = tot[1], Cab = tot[0];  // count and sum above the current bit range
+    if (verdict == 0) {
+        const uint32_t span = Pb - Pa;
+        const int L = 32 - __clz(span);
+        shift = L > 9 ? L - 9 : 0;  // (Pb - base) >> shift < kWinBins
+        base = Pa & ~((1u << shift) - 1u);
+        nb = (int)((Pb - base) >> shift) + 1;
+    }
+    const int total = (int)ctot;
+    // radix levels over the candidates
+    for (int level = 0; level < 5 && verdict == 0; ++level) {
+        for (int b = tid; b < kWinBins; b += kWinThreads) {
+            cnt[b] = 0u;
+            ms[b] = 0ull;
+        }
+        if (tid == 0) best = -1;
+        __syncthreads();
+        const uint32_t lim = base + ((uint32_t)nb << shift);  // exclusive end of the range
+        // the candidates sit in per-block slices written by sweep A; a flat
+        // index maps to a slice by binary search over the prefix sums, so
+        // every thread issues independent loads
+        for (int q = tid; q < total; q += kWinThreads) {
+            int lo = 0, hi = grid_a - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= (uint32_t)q) lo = mid;
+                else hi = mid - 1;
+            }
+            const uint32_t p =
+                __float_as_uint(cand[((int64_t)f * grid_a + lo) * capb + (q - (int)pre[lo])]);
+            if (p >= base && p < lim) {
+                const uint32_t b = (p - base) >> shift;
+                atomicAdd(&cnt[b], 1u);
+                atomicAdd(&ms[b], (unsigned long long)significand(p));
+            }
+        }
+        __syncthreads();
+        // one bin per thread: sums strictly above bin b come from a suffix
+        // scan (a prefix scan in reversed bin order)
+        const int b = kWinBins - 1 - tid;  // reversed
+        const bool valid = b < nb;
+        const double bs = valid ? bin_value(ms[b], base + ((uint32_t)b << shift)) : 0.0;
+        const double bc = valid ? (double)cnt[b] : 0.0;
+        double allS, allC;
+        const double aboveS = Sab + block_exclusive_scan<double>(bs, wsd, allS);
+        const double aboveC = Cab + block_exclusive_scan<double>(bc, wsd, allC);
+        const double radius = s.radius;
+        const double S = aboveS + bs, C = aboveC + bc;  // values >= bin b's first edge
+        const float eb = valid ? __uint_as_float(base + ((uint32_t)b << shift)) : 0.f;
+        const double fb = S - (double)eb * C;
+        if (valid && fb >= radius) atomicMax(&best, b);
+        if (level == 0 && tid == 0) {
+            // tau below the window: f(lo) < radius (every candidate is >= lo)
+            if ((Sab + allS) - (double)s.win_lo * (Cab + allC) < radius) verdict = 2;
+        }
+        __syncthreads();
+        if (verdict == 0) {
+            int bb = best;
+            if (bb < 0 && level == 0) {
+                if (tid == 0) verdict = 2;  // tau below the window
+            } else {
+                if (bb < 0) bb = 0;  // rounding at the lower edge of a deeper range
+                if (b == bb) {
+                    const double Sb = aboveS, Cb = aboveC;  // strictly above bin b
+                    if (fb == radius) {
+                        s.tau = (double)eb;
+                        verdict = 1;
+                    } else if (bc == 0.0 || shift == 0) {
+                        s.tau = (Sb - radius) / Cb;
+                        verdict = 1;
+                    } else if (bc == 1.0) {
+                        const double tl = Cb > 0.0 ? (Sb - radius) / Cb : -1.0;
+                        s.tau = (Cb > 0.0 && tl >= bs) ? tl : (Sb + bs - radius) / (Cb + 1.0);
+                        verdict = 1;
+                    } else {
+                        const int ns = shift > 10 ? shift - 10 : 0;
+                        nbase = base + ((uint32_t)b << shift);
+                        nshift = ns;
+                        nnb = 1 << (shift - ns);
+                        nS = Sb;
+                        nC = Cb;
+                    }
+                }
+            }
+        }
+        __syncthreads();
+        if (verdict == 0) {
+            base = nbase;
+            shift = nshift;
+            nb = nnb;
+            Sab = nS;
+            Cab = nC;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        SelState o = s;
+        if (verdict == 1) {
+            o.done = 1u;
+            o.full = 0u;
+            set_window(o, false);
+        } else {
+            // full radix search on the whole field
+            o.done = 0u;
+            o.full = 1u;
+            o.level = 0u;
+            o.prefix = 0u;
+            o.c_above = 0ull;
+            o.s_above = 0.0;
+            o.win_on = 0u;
+            atomicAdd(fallback_counter, 1u);
+        }
+        sel[f] = o;
+    }
+    if (verdict != 1)
+        for (int q = tid; q < kHistBins; q += kWinThreads) {
+            hist[f].count[q] = 0u;
+            hist[f].msum[q] = 0ull;
+        }
 }
 
 __global__ __launch_bounds__(kSelThreads) void k_soft(const float *x, int64_t n, const SelState *sel,
@@ -258,8 +574,10 @@ __global__ __launch_bounds__(kSelThreads) void k_soft(const float *x, int64_t n,
 
 int hist_blocks(int64_t n)
 {
-    int b = ceil_div(n, (int64_t)kSelThreads * 16);
-    return b < 1 ? 1 : (b > 2048 ? 2048 : b);
+    // small grid: in the solver these launches are no-ops unless the window
+    // missed, and an idle launch costs about its grid size
+    int b = ceil_div(n, (int64_t)kSelThreads * 64);
+    return b < 1 ? 1 : (b > 96 ? 96 : b);
 }
 
 }  // namespace
@@ -276,20 +594,48 @@ hipError_t select_begin(SelState *sel, int nfields, double r0, double r1, Hist *
 hipError_t select_run(const float *z0, const float *z1, int nfields, int64_t n, SelState *sel,
                       Hist *hist, const uint32_t *stop, hipStream_t st)
 {
-    ZPtrs zp;
+    ArraySrc zp;
     zp.z[0] = z0;
     zp.z[1] = z1;
     const int hb = hist_blocks(n);
     for (int level = 0; level < 3; ++level) {
-        hipLaunchKernelGGL(k_hist, dim3(hb, nfields), dim3(kSelThreads), 0, st, zp, n, sel, hist,
-                           level, stop);
+        hipLaunchKernelGGL(k_hist<ArraySrc>, dim3(hb, nfields), dim3(kSelThreads), 0, st, zp, n,
+                           (const SelState *)sel, hist, level, stop);
         hipLaunchKernelGGL(k_select_level, dim3(nfields), dim3(kSelThreads), 0, st, sel, hist,
                            level, stop);
-        if (level < 2)
-            hipLaunchKernelGGL(k_hist_clear, dim3(nfields), dim3(kSelThreads), 0, st, hist,
-                               nfields, sel, stop);
     }
     return hipGetLastError();
+}
+
+template <typename DT>
+hipError_t solver_select_t(const ZState &zs, SelState *sel, Hist *hist, const double *winpart,
+                           int grid_a, const float *cand, const uint32_t *ccount, int capb,
+                           const uint32_t *stop, uint32_t *fallback_counter, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_select_window, dim3(2), dim3(kWinThreads), 0, st, sel, hist, winpart,
+                       grid_a, cand, ccount, capb, stop, fallback_counter);
+    StateSrc<DT> src;
+    src.zs = zs;
+    src.par = 0;
+    src.c4 = src.d4v = 0.f;
+    const int hb = hist_blocks(zs.d.plane);
+    for (int level = 0; level < 3; ++level) {
+        hipLaunchKernelGGL(k_hist<StateSrc<DT>>, dim3(hb, 2), dim3(kSelThreads), 0, st, src,
+                           zs.d.plane, (const SelState *)sel, hist, level, stop);
+        hipLaunchKernelGGL(k_select_level, dim3(2), dim3(kSelThreads), 0, st, sel, hist, level, stop);
+    }
+    return hipGetLastError();
+}
+
+hipError_t solver_select(const ZState &zs, SelState *sel, Hist *hist, const double *winpart,
+                         int grid_a, const float *cand, const uint32_t *ccount, int capb,
+                         const uint32_t *stop, uint32_t *fallback_counter, hipStream_t st)
+{
+    return zs.dual_bytes == 2
+               ? solver_select_t<bf16>(zs, sel, hist, winpart, grid_a, cand, ccount, capb, stop,
+                                       fallback_counter, st)
+               : solver_select_t<float>(zs, sel, hist, winpart, grid_a, cand, ccount, capb, stop,
+                                        fallback_counter, st);
 }
 
 hipError_t launch_l1_threshold(const float *x, int64_t n, double radius, SelState *sel, Hist *hist,

@@ -11,17 +11,27 @@
 
 namespace geo {
 
-// Exact l1-ball threshold search state for one field (radix search over the
-// FP32 bit patterns of |z|, see select.hip).
+// Exact l1-ball threshold search state for one field. In steady state the
+// level tau moves little between iterations: sweep A collects the values of
+// |z| inside a window [win_lo, win_hi] predicted from the last two levels
+// (candidates) plus the count and sum of the values above it, and one block
+// finishes the search exactly over the candidates. When the window misses,
+// a radix search over the FP32 bit patterns of the whole field runs instead
+// (see select.hip).
 struct SelState {
     double radius;     // radius of the l1 ball
-    double s_above;    // sum of |z| over values above the current bit range
-    double tau;        // final soft-threshold level
-    uint64_t c_above;  // count of those values
-    uint32_t prefix;   // pattern bits fixed so far
-    uint32_t done;     // tau final
+    double s_above;    // radix search: sum of |z| above the current bit range
+    double tau;        // soft-threshold level of this iteration
+    double tau_prev;   // level of the previous iteration (window prediction)
+    double tau_prev2;  // and of the one before
+    uint64_t c_above;  // radix search: count of those values
+    uint32_t prefix;   // radix search: pattern bits fixed so far
+    uint32_t done;     // tau final for this iteration
     uint32_t level;    // next radix level (0, 1, 2)
-    uint32_t pad;
+    uint32_t full;     // 1 when the radix search over the full field runs
+    float win_lo, win_hi;  // window used by the next sweep A
+    uint32_t win_on;       // window valid
+    uint32_t cand_count;   // candidates in the window (search bookkeeping)
 };
 
 constexpr int kHistBins = 2048;  // bins of radix level 0 (levels 1 and 2 use 1024)
@@ -47,43 +57,64 @@ struct DevScalars {
     uint32_t nonfinite;  // NaN/Inf seen
     uint32_t calls_iter; // iterations done in the current geo_step call
     SelState sel[2];     // 0: s (alpha), 1: t (beta)
-    uint32_t fallback;   // extra threshold passes in the current call
+    uint32_t fallback;   // full radix searches in the current call
     uint32_t pad[3];
 };
 
 // Offsets (bytes) of every region of a solver workspace.
 struct Layout {
-    size_t scalars, partials, hist, y4p, zs, zt;
+    size_t scalars, partials, hist, y4p, winpart, cand, ccount;
     size_t u[2], s[2], t[2], w1[2], w2[2];  // FP32 primal, ping-pong
     size_t y1[2], y2[2], y3[2], y4[2];      // duals (FP32 or BF16), ping-pong
     size_t total;
     int dual_bytes;
-    int n_part;  // number of FP64 partial-sum slots
+    int n_part;    // FP64 partial-sum slots
+    int max_grid;  // upper bound of the sweep A grid
+    int64_t cap;   // candidate capacity per field
 };
 
 // Tile of the fused primal/dual sweep.
-constexpr int kTI = 8, kTJ = 64, kKC = 16, kSweepThreads = 256;
+constexpr int kTI = 8, kTJ = 64, kKC = 8, kSweepThreads = 512;
 constexpr int kPointThreads = 256;
+constexpr int kMaxSweepGrid = 2048;  // persistent grid bound (256 CUs x 8)
+constexpr int kSweepBBlocks = 2048;  // grid-stride blocks of sweep B
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 struct SweepGrid {
     int tj, ti, tk;  // tiles along j, i and band chunks
-    int blocks() const { return tj * ti * tk; }
+    __host__ __device__ int blocks() const { return tj * ti * tk; }
 };
 inline SweepGrid sweep_grid(int n1, int n2, int n3)
 {
     return SweepGrid{ceil_div(n2, kTJ), ceil_div(n1, kTI), ceil_div(n3, kKC)};
 }
 inline int point_blocks(int64_t n) { return ceil_div(n, kPointThreads); }
+inline int sweep_b_blocks(int64_t n)
+{
+    int b = point_blocks(n);
+    return b < kSweepBBlocks ? b : kSweepBBlocks;
+}
+inline int sweep_a_max_grid(int n1, int n2, int n3)
+{
+    int t = sweep_grid(n1, n2, n3).blocks();
+    return t < kMaxSweepGrid ? t : kMaxSweepGrid;
+}
 
 Layout make_layout(int n1, int n2, int n3, int dual_storage);
 
-// Pointers of one ping-pong side.
+// Pointers of one ping-pong side. Inside the workspace the two components
+// of each dual edge field and of each l_{1,2} group of w sit together:
+//   y1, y2 : N pairs (vertical, horizontal)
+//   w1, w2 : 3 planes of N pairs, one plane per grid (ud, lr, c)
+// (the ABI's state accessors convert to and from separate planes).
 template <typename DT>
 struct Side {
-    float *u, *s, *t, *w1, *w2;
-    DT *y1, *y2, *y3, *y4;
+    using P = typename PairOf<DT>::type;
+    float *u, *s, *t;
+    float2 *w1, *w2;
+    P *y1, *y2;
+    DT *y3, *y4;
 };
 
 struct IterParams {
@@ -92,8 +123,9 @@ struct IterParams {
 
 // ---- launchers (kernels in sweep.hip / select.hip / ops.hip) ----
 hipError_t launch_init(const Dims &d, const float *v, void *ws, const Layout &L, double eps,
-                       double tol, hipStream_t st);
-hipError_t launch_begin_call(void *ws, const Layout &L, double tol, hipStream_t st);
+                       double tol, double alpha, double beta, hipStream_t st);
+hipError_t launch_begin_call(void *ws, const Layout &L, double tol, double alpha, double beta,
+                             hipStream_t st);
 // ev (may be null): 5 events recorded at the phase boundaries
 // (before sweep A, after sweep A, after the threshold search, after sweep B,
 // after finalize).
@@ -114,6 +146,21 @@ hipError_t select_run(const float *z0, const float *z1, int nfields, int64_t n, 
 hipError_t launch_l1_threshold(const float *x, int64_t n, double radius, SelState *sel,
                                Hist *hist, hipStream_t st);
 hipError_t launch_soft(const float *x, int64_t n, const SelState *sel, float *out, hipStream_t st);
+
+// The solver's per-iteration search: window pass over the candidates, then
+// the full radix search on z evaluated from the state (no-op when the
+// window held tau).
+struct ZState {
+    Dims d;
+    const float *v;
+    const float *s[2], *t[2];   // ping-pong sides
+    const void *y3[2], *y4[2];  // FP32 or BF16 (dual_bytes)
+    int dual_bytes;
+    const DevScalars *sc;       // iteration parity and the lazy y4 factors
+};
+hipError_t solver_select(const ZState &zs, SelState *sel, Hist *hist, const double *winpart,
+                         int grid_a, const float *cand, const uint32_t *ccount, int capb,
+                         const uint32_t *stop, uint32_t *fallback_counter, hipStream_t st);
 
 // Standalone projections (ops.hip).
 int l2_blocks(int64_t n);

@@ -1,10 +1,12 @@
 // One iteration of Alg. 1 (problem (20)) as HBM-streaming sweeps for gfx950.
 //
 //   sweep A  (fused, LDS-tiled): steps 1, 4, 5, the extrapolations 6 and 9-10,
-//            steps 11 and 12, the u' part of step 14, and the inputs of the
-//            two l1-ball projections (z_s of step 2, z_t of step 3) plus the
-//            FP64 partial sums of the stopping rule (eq. (28)).
-//   select   (select.hip): exact soft-threshold levels tau_s, tau_t.
+//            steps 11 and 12 and the u' part of step 14; it also evaluates the
+//            inputs z_s, z_t of the two l1-ball projections (steps 2, 3) and
+//            feeds the threshold search (count and sum above a predicted
+//            window, values inside it), plus the FP64 partial sums of the
+//            stopping rule (eq. (28)).
+//   search   (select.hip): exact soft-threshold levels tau_s, tau_t.
 //   sweep B  (pointwise): steps 2, 3, 7, 8, 13, the rest of step 14 and the
 //            FP64 partial sums of the l2-ball distance of step 15.
 //   finalize (one block): the l2-ball factor of step 15 (applied lazily when
@@ -12,16 +14,18 @@
 //
 // Sweep A keeps the w1/w2 extrapolations (12 of the 21 state words per voxel)
 // out of HBM: a workgroup owns a TI x TJ pixel tile and marches through a
-// chunk of bands; for each band it stages the masked dual edge fields y1, y2
-// with a 2-pixel halo in LDS, recomputes w' on a 1-pixel ring and u' on the
-// (i+1, j+1) ring, and updates y1, y2 from LDS. The D_s coupling between bands
-// is carried in LDS from one band to the next.
+// chunk of bands. Per band it stages the masked dual edge fields y1, y2 with
+// a 2-pixel halo in LDS, recomputes w' on a 1-pixel ring and u' on the
+// (i+1, j+1) ring, and updates y1, y2 from LDS; the D_s coupling of
+// neighbouring bands is carried in LDS. Global loads of band k+1 (w) and
+// k+2 (y, u, v, y4, s, t, y3) are issued while band k is computed, so the
+// memory latency overlaps the arithmetic.
 //
 // Every state array is ping-ponged: iteration k reads side (k & 1) and writes
-// side ((k + 1) & 1), so halo reads never race with writes. The side is taken
+// side ((k + 1) & 1), so halo reads never race with writes. The side comes
 // from the device iteration counter, which makes one iteration's launches a
-// fixed sequence (and the stopping rule a device flag that turns the rest of
-// the launches into no-ops, so iteration counts stay exact).
+// fixed sequence; once the stopping rule holds a device flag turns the
+// remaining launches into no-ops, so iteration counts stay exact.
 #include "solver.hpp"
 
 namespace geo {
@@ -29,145 +33,285 @@ namespace geo {
 namespace {
 
 constexpr int TI = kTI, TJ = kTJ, KC = kKC, NT = kSweepThreads;
-constexpr int H2 = TI + 4, W2 = TJ + 4, S2 = H2 * W2;  // y halo 2
-constexpr int H1 = TI + 2, W1 = TJ + 2, S1 = H1 * W1;  // w' ring 1
-constexpr int HU = TI + 1, WU = TJ + 1, SU = HU * WU;  // u' ring (+1, +1)
+constexpr int H2 = TI + 4, W2 = TJ + 4, S2 = H2 * W2;  // y with a 2-pixel halo
+constexpr int H1 = TI + 2, W1 = TJ + 2, S1 = H1 * W1;  // w' on a 1-pixel ring
+constexpr int HU = TI + 1, WU = TJ + 1, SU = HU * WU;  // u' with the (+1, +1) ring
+constexpr int NY = (S2 + NT - 1) / NT;                  // y points per thread
+constexpr int RING1 = S1 - TI * TJ;                     // w' ring points
+constexpr int RINGU = SU - TI * TJ;                     // u' ring points
+static_assert(TI * TJ == NT && TJ == 64, "one own point per thread, a wave per tile row");
+static_assert(RING1 <= NT && RINGU <= NT, "at most one ring point per thread");
+constexpr int NPT = 256;  // threads of the pointwise kernels
 
 template <typename DT>
 struct IterArgs {
     Dims d;
     const float *v;
     Side<DT> side[2];
-    DT *y4p;  // y4 + u'/5 (step 14, first part)
-    float *zs, *zt;
+    DT *y4p;         // y4 + u'/5 (step 14, first part)
     DevScalars *sc;
-    double *part;  // [blocks_a * 2 | blocks_b]
-    int blocks_a;
+    double *part;    // [grid_a * 2 | blocks_b]
+    double *winpart; // [2][grid_a][3]: count above, sum above, sum of |z|
+    float *cand;     // [2][grid_a][capb]: per-block slices of candidates
+    uint32_t *ccount;// [2][grid_a]: candidates appended by each block
+    int capb;
+    int grid_a, blocks_b;
     SweepGrid g;
-    float thr1;  // omega * step_w1
+    float thr1;      // omega * step_w1
     float mu_lo, mu_hi;
 };
 
-// Block -> tile. Workgroups are dispatched round-robin over the 8 XCDs; give
-// each XCD a contiguous run of tiles (j fastest, then i, then band chunk) so
-// that halo rows shared by neighbouring tiles meet in the same L2.
-__device__ __forceinline__ void tile_of(const SweepGrid &g, int &tj, int &ti, int &tk)
+// Value as stored (FP32 or rounded to BF16), for the l2-ball distance.
+__device__ __forceinline__ float as_stored(const float *, float x) { return x; }
+__device__ __forceinline__ float as_stored(const bf16 *, float x)
 {
-    const int nb = g.tj * g.ti * g.tk;
-    const int b = blockIdx.x;
-    int t = b;
-    if (nb >= 64) {
-        const int xcd = b & 7, slot = b >> 3;
-        const int per = nb >> 3, rem = nb & 7;
-        // XCDs 0..rem-1 own per+1 tiles, the rest per tiles
-        t = xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+    bf16 b;
+    st(&b, x);
+    return ld(&b);
+}
+
+// Append val to this block's slice of a field's candidate list. The slot
+// comes from an LDS counter (wavefront-aggregated), so sweep A never waits on
+// a global atomic; entries past the slice's capacity are counted but
+// dropped, which the search detects as an overflow. Every lane of the
+// wavefront must call it.
+__device__ __forceinline__ void wave_append(bool want, float val, float *slice, uint32_t *lds_count,
+                                            int capb)
+{
+    const unsigned long long m = __ballot(want);
+    if (m == 0ull) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0u;
+    if (lane == leader) base = atomicAdd(lds_count, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    const uint32_t off = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (want && base + off < (uint32_t)capb) slice[base + off] = val;
+}
+
+// XCD-aware persistent tile order: the 8 XCDs take contiguous tile ranges so
+// that the halos shared by neighbouring tiles meet in the same L2.
+__device__ __forceinline__ int tile_at(int b, int G, int T, int r)
+{
+    if (G >= 8 && (G & 7) == 0) {
+        const int x = b & 7, slot = b >> 3, per = G >> 3;
+        const int lo = (int)(((int64_t)x * T) >> 3), hi = (int)(((int64_t)(x + 1) * T) >> 3);
+        const int t = lo + slot + r * per;
+        return t < hi ? t : -1;
     }
-    tj = t % g.tj;
-    const int r = t / g.tj;
-    ti = r % g.ti;
-    tk = r / g.ti;
+    const int t = b + r * G;
+    return t < T ? t : -1;
 }
 
 template <typename DT>
-__global__ __launch_bounds__(NT) void k_sweep_a(IterArgs<DT> a)
+__global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
 {
-    const DevScalars *sc = a.sc;
+    using P = typename PairOf<DT>::type;
+    DevScalars *sc = a.sc;
     if (sc->stop) return;
-    __shared__ float sY[2][4][S2];  // [band parity][y1v, y1h, y2v, y2h] masked
+    __shared__ float sY[2][4][S2];  // [band parity][y1v, y1h, y2v, y2h], masked
     __shared__ float sU[2][SU];     // u' by band parity
-    __shared__ float sW[2][6][S1];  // w1', w2' (masked ud/lr planes)
+    __shared__ float sW[2][4][S1];  // w1', w2' planes read by neighbours: ud_h, lr_v, c_v, c_h
     __shared__ double red[NT / 64];
+    __shared__ uint32_t ncand[2];
 
     const Dims d = a.d;
     const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
-    const int64_t N = d.plane;
+    const uint32_t N = (uint32_t)d.plane;
+    if (threadIdx.x < 2) ncand[threadIdx.x] = 0u;  // published by the first barrier
     const int par = (int)(sc->iter & 1u);
     const Side<DT> src = a.side[par], dst = a.side[par ^ 1];
     const float c4 = (float)sc->c4, d4v = (float)(sc->d4 * 0.2);
-    int tj, ti, tk;
-    tile_of(a.g, tj, ti, tk);
-    const int j0 = tj * TJ, i0 = ti * TI, kb = tk * KC;
-    const int ke = min(kb + KC, n3);
     const int tid = threadIdx.x;
+    const int oti = tid / TJ, otj = tid % TJ;  // the thread's own point in the tile
+    auto vox32 = [&](int k, int i, int j) {
+        return ((uint32_t)k * (uint32_t)n1 + (uint32_t)i) * (uint32_t)n2 + (uint32_t)j;
+    };
+    float wlo[2], whi[2];
+    bool won[2];
+    for (int f = 0; f < 2; ++f) {
+        won[f] = sc->sel[f].win_on != 0u;
+        wlo[f] = sc->sel[f].win_lo;
+        whi[f] = sc->sel[f].win_hi;
+    }
     double du2 = 0.0, u2 = 0.0;
+    double s_hi[2] = {0.0, 0.0}, s_all[2] = {0.0, 0.0};
+    float c_hi[2] = {0.f, 0.f};
 
-    auto loadY = [&](int k, int buf) {
-        for (int p = tid; p < S2; p += NT) {
-            const int li = p / W2, lj = p - li * W2;
-            const int i = i0 - 2 + li, j = j0 - 2 + lj;
-            float a1 = 0.f, b1 = 0.f, a2 = 0.f, b2 = 0.f;
-            if (k >= 0 && k < n3 && i >= 0 && i < n1 && j >= 0 && j < n2) {
-                const int64_t q = vox(d, k, i, j);
-                if (i <= n1 - 2) {
-                    a1 = ld(src.y1 + q);
-                    a2 = ld(src.y2 + q);
+    // ring coordinates (R1-local for w', RU-local for u')
+    int rwi = 0, rwj = 0, rui = 0, ruj = 0;
+    if (tid < RING1) {
+        if (tid < W1) { rwi = 0; rwj = tid; }
+        else if (tid < 2 * W1) { rwi = H1 - 1; rwj = tid - W1; }
+        else { const int s = tid - 2 * W1; rwi = 1 + (s >> 1); rwj = (s & 1) ? W1 - 1 : 0; }
+    }
+    if (tid < RINGU) {
+        if (tid < WU) { rui = TI; ruj = tid; }
+        else { rui = tid - WU; ruj = TJ; }
+    }
+    const bool ring_w = tid < RING1, ring_u = tid < RINGU;
+
+    const int T = a.g.blocks();
+    for (int r = 0;; ++r) {
+        const int t = tile_at(blockIdx.x, a.grid_a, T, r);
+        if (t < 0) break;
+        const int tj = t % a.g.tj, rest = t / a.g.tj;
+        const int j0 = tj * TJ, i0 = (rest % a.g.ti) * TI, kb = (rest / a.g.ti) * KC;
+        const int ke = min(kb + KC, n3);
+        const int oi = i0 + oti, oj = j0 + otj;
+        const bool own_in = oi < n1 && oj < n2;
+
+        // ---------------- register staging of global loads ----------------
+        float2 ry1[NY], ry2[NY];
+        auto loadY = [&](int k) {
+#pragma unroll
+            for (int n = 0; n < NY; ++n) {
+                const int p = tid + NT * n;
+                const int li = p / W2, lj = p - li * W2;
+                const int i = i0 - 2 + li, j = j0 - 2 + lj;
+                float2 y1 = make_float2(0.f, 0.f), y2 = y1;
+                if (p < S2 && k >= 0 && k < n3 && i >= 0 && i < n1 && j >= 0 && j < n2) {
+                    const uint32_t q = vox32(k, i, j);
+                    y1 = ld2(src.y1 + q);
+                    y2 = ld2(src.y2 + q);
+                    if (i > n1 - 2) y1.x = y2.x = 0.f;  // masked: last row (vertical)
+                    if (j > n2 - 2) y1.y = y2.y = 0.f;  // masked: last column (horizontal)
                 }
-                if (j <= n2 - 2) {
-                    b1 = ld(src.y1 + N + q);
-                    b2 = ld(src.y2 + N + q);
+                ry1[n] = y1;
+                ry2[n] = y2;
+            }
+        };
+        auto storeY = [&](int buf) {
+#pragma unroll
+            for (int n = 0; n < NY; ++n) {
+                const int p = tid + NT * n;
+                if (p < S2) {
+                    sY[buf][0][p] = ry1[n].x;
+                    sY[buf][1][p] = ry1[n].y;
+                    sY[buf][2][p] = ry2[n].x;
+                    sY[buf][3][p] = ry2[n].y;
                 }
             }
-            sY[buf][0][p] = a1;
-            sY[buf][1][p] = b1;
-            sY[buf][2][p] = a2;
-            sY[buf][3][p] = b2;
-        }
-    };
-    // D^T (y_v, y_h) at R2-local (li, lj) from the masked fields in LDS
-    auto dT = [&](int buf, int pv, int li, int lj) {
-        const float *yv = sY[buf][pv], *yh = sY[buf][pv + 1];
-        const int c = li * W2 + lj;
-        return (yv[c - W2] - yv[c]) + (yh[c - 1] - yh[c]);
-    };
-    // u+ and u' for band kk on the (i+1, j+1) ring; own points also write
-    // u+, y4 + u'/5 and the l1-projection inputs z_s, z_t of band kk.
-    auto uphase = [&](int kk, bool own_band) {
-        const int buf = kk & 1;
-        for (int p = tid; p < SU; p += NT) {
-            const int ui = p / WU, uj = p - ui * WU;
-            const int i = i0 + ui, j = j0 + uj;
-            float up = 0.f;
-            if (kk < n3 && i < n1 && j < n2) {
-                const int li = ui + 2, lj = uj + 2;
-                // D^T y1 + D_s^T D^T y2 at band kk
-                float g = dT(buf, 0, li, lj);
-                if (kk <= n3 - 2) g -= dT(buf, 2, li, lj);
-                if (kk >= 1) g += dT(buf ^ 1, 2, li, lj);
-                const int64_t q = vox(d, kk, i, j);
-                const float vq = a.v[q];
-                const float y4 = c4 * (ld(src.y4 + q) - d4v * vq);
-                const float uo = src.u[q];
-                const float x = uo - kStepU * (g + y4);
-                const float un = x < a.mu_lo ? a.mu_lo : (x > a.mu_hi ? a.mu_hi : x);
-                up = 2.f * un - uo;
-                if (own_band && ui < TI && uj < TJ) {
+        };
+        // u, y4 (stored), v at the own point and the u' ring point; s, t,
+        // y3 (row and row above) at the own point
+        float ru_u, ru_y4, ru_v, ru_s, ru_t, ru_y3c, ru_y3m, rr_u, rr_y4, rr_v;
+        auto loadRU = [&](int kk) {
+            ru_u = ru_y4 = ru_v = ru_s = ru_t = ru_y3c = ru_y3m = 0.f;
+            if (kk < n3 && own_in) {
+                const uint32_t q = vox32(kk, oi, oj);
+                ru_u = src.u[q];
+                ru_y4 = ld(src.y4 + q);
+                ru_v = a.v[q];
+                ru_s = src.s[q];
+                ru_t = src.t[q];
+                ru_y3c = oi <= n1 - 2 ? ld(src.y3 + q) : 0.f;
+                ru_y3m = oi >= 1 ? ld(src.y3 + q - n2) : 0.f;
+            }
+            rr_u = rr_y4 = rr_v = 0.f;
+            const int i = i0 + rui, j = j0 + ruj;
+            if (ring_u && kk < n3 && i < n1 && j < n2) {
+                const uint32_t q = vox32(kk, i, j);
+                rr_u = src.u[q];
+                rr_y4 = ld(src.y4 + q);
+                rr_v = a.v[q];
+            }
+        };
+        // w1, w2 (3 pairs each) at the own point and the w' ring point
+        float2 rw[2][2][3];  // [own, ring][field][grid]
+        auto loadW = [&](int k) {
+#pragma unroll
+            for (int o = 0; o < 2; ++o) {
+                const int i = o == 0 ? oi : i0 - 1 + rwi, j = o == 0 ? oj : j0 - 1 + rwj;
+                const bool in = (o == 0 ? true : ring_w) && i >= 0 && i < n1 && j >= 0 && j < n2 && k < n3;
+                const uint32_t q = in ? vox32(k, i, j) : 0u;
+#pragma unroll
+                for (int g = 0; g < 3; ++g) {
+                    rw[o][0][g] = in ? (src.w1 + (size_t)g * N)[q] : make_float2(0.f, 0.f);
+                    rw[o][1][g] = in ? (src.w2 + (size_t)g * N)[q] : make_float2(0.f, 0.f);
+                }
+            }
+        };
+
+        // ---------------- phases ----------------
+        auto dT = [&](int buf, int pv, int c) {
+            const float *yv = sY[buf][pv], *yh = sY[buf][pv + 1];
+            return (yv[c - W2] - yv[c]) + (yh[c - 1] - yh[c]);
+        };
+        // u+ of step 1 and u' at one point of band kk
+        auto u_at = [&](int kk, int ui, int uj, float uo, float y4s, float vq, float &y4) {
+            const int buf = kk & 1;
+            const int c = (ui + 2) * W2 + (uj + 2);
+            float g = dT(buf, 0, c);                  // D^T y1
+            if (kk <= n3 - 2) g -= dT(buf, 2, c);      // D_s^T D^T y2
+            if (kk >= 1) g += dT(buf ^ 1, 2, c);
+            y4 = y4_of(y4s, vq, c4, d4v);
+            const float x = uo - kStepU * (g + y4);
+            return x < a.mu_lo ? a.mu_lo : (x > a.mu_hi ? a.mu_hi : x);
+        };
+        // step 1 (u+), u' and the z inputs of steps 2, 3 for band kk
+        auto uphase = [&](int kk, bool own_band) {
+            const int buf = kk & 1;
+            float up = 0.f, zs = 0.f, zt = 0.f;
+            bool wr = false;
+            if (kk < n3 && own_in) {
+                float y4;
+                const float un = u_at(kk, oti, otj, ru_u, ru_y4, ru_v, y4);
+                up = 2.f * un - ru_u;
+                if (own_band) {
+                    wr = true;
+                    const uint32_t q = vox32(kk, oi, oj);
                     dst.u[q] = un;
                     st(a.y4p + q, y4 + kStepY * up);
-                    const float dl = un - uo;
-                    du2 += (double)dl * (double)dl;
-                    u2 += (double)uo * (double)uo;
-                    const float y3c = i <= n1 - 2 ? ld(src.y3 + q) : 0.f;
-                    const float y3m = i >= 1 ? ld(src.y3 + q - n2) : 0.f;
-                    a.zs[q] = src.s[q] - y4;                          // step 2 (gamma_s = 1)
-                    a.zt[q] = src.t[q] - kStepT * ((y3m - y3c) + y4);  // step 3
+                    const float dl = un - ru_u;
+                    du2 += (double)(dl * dl);
+                    u2 += (double)(ru_u * ru_u);
+                    zs = zs_of(ru_s, y4);
+                    zt = zt_of(ru_t, ru_y3m, ru_y3c, y4);
                 }
             }
-            sU[buf][p] = up;
-        }
-    };
-    // w1+, w2+ (steps 4, 5) and w' (steps 9, 10) on the 1-pixel ring of band k
-    auto wphase = [&](int k) {
-        const int buf = k & 1;
-        for (int p = tid; p < S1; p += NT) {
-            const int wi = p / W1, wj = p - wi * W1;
-            const int i = i0 - 1 + wi, j = j0 - 1 + wj;
-            const bool in = i >= 0 && i < n1 && j >= 0 && j < n2;
-            const bool own = wi >= 1 && wi <= TI && wj >= 1 && wj <= TJ;
-            const float mv = mask_le(i, n1), mh = mask_le(j, n2);
-            const int c = (wi + 1) * W2 + (wj + 1);
+            sU[buf][oti * WU + otj] = up;
+            if (ring_u) {
+                float upr = 0.f;
+                if (kk < n3 && i0 + rui < n1 && j0 + ruj < n2) {
+                    float y4;
+                    const float un = u_at(kk, rui, ruj, rr_u, rr_y4, rr_v, y4);
+                    upr = 2.f * un - rr_u;
+                }
+                sU[buf][rui * WU + ruj] = upr;
+            }
+            // threshold-search inputs (every lane takes part)
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
-                float o[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+                const float av = fabsf(f ? zt : zs);
+                bool cand = false;
+                if (wr) {
+                    s_all[f] += (double)av;
+                    if (won[f]) {
+                        if (av > whi[f]) {
+                            c_hi[f] += 1.f;
+                            s_hi[f] += (double)av;
+                        } else if (av >= wlo[f]) {
+                            cand = true;
+                        }
+                    }
+                }
+                wave_append(cand, av, a.cand + ((int64_t)f * a.grid_a + blockIdx.x) * a.capb,
+                            &ncand[f], a.capb);
+            }
+        };
+        // steps 4, 5 and the w extrapolations (9, 10) at one point of band k;
+        // own: also writes w+ and returns the own-only planes ud_v', lr_h'
+        float wk[2][2];
+        auto w_at = [&](int k, int o, int wi, int wj, bool act) {
+            const int buf = k & 1;
+            const int i = i0 - 1 + wi, j = j0 - 1 + wj;
+            const bool in = act && i >= 0 && i < n1 && j >= 0 && j < n2;
+            const float mv = mask_le(i, n1), mh = mask_le(j, n2);
+            const int c = (wi + 1) * W2 + (wj + 1), c1 = wi * W1 + wj;
+#pragma unroll
+            for (int f = 0; f < 2; ++f) {
+                float o6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
                 if (in) {
                     const float *yv = sY[buf][2 * f], *yh = sY[buf][2 * f + 1];
                     float L[6];
@@ -177,86 +321,129 @@ __global__ __launch_bounds__(NT) void k_sweep_a(IterArgs<DT> a)
                     L[3] = mh * yh[c];
                     L[4] = 0.5f * (yv[c] + yv[c - W2]);
                     L[5] = 0.5f * (yh[c] + yh[c - 1]);
-                    const int64_t q = vox(d, k, i, j);
-                    const float *w = f ? src.w2 : src.w1;
-                    float *wd = f ? dst.w2 : dst.w1;
                     const float thr = f ? kStepW : a.thr1;
                     float wo[6], wn[6];
 #pragma unroll
-                    for (int cc = 0; cc < 6; ++cc) {
-                        wo[cc] = w[cc * N + q];
-                        wn[cc] = wo[cc] + kStepW * L[cc];
+                    for (int g = 0; g < 3; ++g) {
+                        wo[2 * g] = rw[o][f][g].x;
+                        wo[2 * g + 1] = rw[o][f][g].y;
                     }
+#pragma unroll
+                    for (int cc = 0; cc < 6; ++cc) wn[cc] = wo[cc] + kStepW * L[cc];
                     shrink2(wn[0], wn[1], thr);
                     shrink2(wn[2], wn[3], thr);
                     shrink2(wn[4], wn[5], thr);
-                    if (own) {
+                    if (o == 0) {
+                        const uint32_t q = vox32(k, i, j);
+                        float2 *wd = f ? dst.w2 : dst.w1;
 #pragma unroll
-                        for (int cc = 0; cc < 6; ++cc) wd[cc * N + q] = wn[cc];
+                        for (int g = 0; g < 3; ++g) (wd + (size_t)g * N)[q] = make_float2(wn[2 * g], wn[2 * g + 1]);
                     }
 #pragma unroll
-                    for (int cc = 0; cc < 6; ++cc) o[cc] = 2.f * wn[cc] - wo[cc];
-                    o[0] *= mv;
-                    o[1] *= mv;
-                    o[2] *= mh;
-                    o[3] *= mh;
+                    for (int cc = 0; cc < 6; ++cc) o6[cc] = 2.f * wn[cc] - wo[cc];
+                    o6[0] *= mv;
+                    o6[1] *= mv;
+                    o6[2] *= mh;
+                    o6[3] *= mh;
                 }
-#pragma unroll
-                for (int cc = 0; cc < 6; ++cc) sW[f][cc][p] = o[cc];
+                if (act) {
+                    sW[f][0][c1] = o6[1];
+                    sW[f][1][c1] = o6[2];
+                    sW[f][2][c1] = o6[4];
+                    sW[f][3][c1] = o6[5];
+                }
+                if (o == 0) {
+                    wk[f][0] = o6[0];
+                    wk[f][1] = o6[3];
+                }
             }
-        }
-    };
-    // y1+, y2+ (steps 11, 12) of band k on the tile
-    auto yphase = [&](int k) {
-        const float msk = k <= n3 - 2 ? 1.f : 0.f;
-        for (int p = tid; p < TI * TJ; p += NT) {
-            const int ti_ = p / TJ, tj_ = p - ti_ * TJ;
-            const int i = i0 + ti_, j = j0 + tj_;
-            if (i >= n1 || j >= n2) continue;
-            const float mv = mask_le(i, n1), mh = mask_le(j, n2);
-            const int c = (ti_ + 1) * W1 + (tj_ + 1);
-            const int cu = ti_ * WU + tj_;
-            const float *u0 = sU[k & 1], *u1 = sU[(k + 1) & 1];
+        };
+        auto wphase = [&](int k) {
+            w_at(k, 0, oti + 1, otj + 1, true);
+            if (ring_w) w_at(k, 1, rwi, rwj, true);
+        };
+        // steps 11, 12 for band k at the own point
+        auto yphase = [&](int k) {
+            if (!own_in) return;
+            const float msk = k <= n3 - 2 ? 1.f : 0.f;
+            const int buf = k & 1;
+            const float mv = mask_le(oi, n1), mh = mask_le(oj, n2);
+            const int c1 = (oti + 1) * W1 + (otj + 1);
+            const int c2 = (oti + 2) * W2 + (otj + 2);
+            const int cu = oti * WU + otj;
+            const float *u0 = sU[buf], *u1 = sU[buf ^ 1];
             const float du_v = mv * (u0[cu + WU] - u0[cu]), du_h = mh * (u0[cu + 1] - u0[cu]);
             const float dn_v = mv * (u1[cu + WU] - u1[cu]), dn_h = mh * (u1[cu + 1] - u1[cu]);
-            const int64_t q = vox(d, k, i, j);
+            const uint32_t q = vox32(k, oi, oj);
 #pragma unroll
             for (int f = 0; f < 2; ++f) {
                 const float(*W)[S1] = sW[f];
-                const float pv = mv * (W[0][c] + 0.25f * ((W[2][c] + W[2][c + W1]) + (W[2][c - 1] + W[2][c + W1 - 1]))
-                                       + 0.5f * (W[4][c] + W[4][c + W1]));
-                const float ph = mh * (W[3][c] + 0.25f * ((W[1][c] + W[1][c + 1]) + (W[1][c - W1] + W[1][c - W1 + 1]))
-                                       + 0.5f * (W[5][c] + W[5][c + 1]));
-                const DT *ys = f ? src.y2 : src.y1;
-                DT *yd = f ? dst.y2 : dst.y1;
+                const float pv = mv * (wk[f][0] + 0.25f * ((W[1][c1] + W[1][c1 + W1]) + (W[1][c1 - 1] + W[1][c1 + W1 - 1]))
+                                       + 0.5f * (W[2][c1] + W[2][c1 + W1]));
+                const float ph = mh * (wk[f][1] + 0.25f * ((W[0][c1] + W[0][c1 + 1]) + (W[0][c1 - W1] + W[0][c1 - W1 + 1]))
+                                       + 0.5f * (W[3][c1] + W[3][c1 + 1]));
+                const P *ys = f ? src.y2 : src.y1;
+                P *yd = f ? dst.y2 : dst.y1;
+                float2 y = make_float2(sY[buf][2 * f][c2], sY[buf][2 * f + 1][c2]);
+                // masked entries (last row / column) keep their stored value
+                if (oi > n1 - 2 || oj > n2 - 2) {
+                    const float2 raw = ld2(ys + q);
+                    if (oi > n1 - 2) y.x = raw.x;
+                    if (oj > n2 - 2) y.y = raw.y;
+                }
                 const float gv = f ? msk * (dn_v - du_v) : du_v;
                 const float gh = f ? msk * (dn_h - du_h) : du_h;
-                st(yd + q, ld(ys + q) + kStepY * (gv - pv));
-                st(yd + N + q, ld(ys + N + q) + kStepY * (gh - ph));
+                st2(yd + q, make_float2(y.x + kStepY * (gv - pv), y.y + kStepY * (gh - ph)));
             }
-        }
-    };
+        };
 
-    // prologue: bands kb-1 (for D_s^T at kb) and kb, then u' of band kb
-    if (kb >= 1) loadY(kb - 1, (kb - 1) & 1);
-    loadY(kb, kb & 1);
-    __syncthreads();
-    uphase(kb, true);
-    __syncthreads();
-    for (int k = kb; k < ke; ++k) {
-        loadY(k + 1, (k + 1) & 1);  // zeros beyond the last band
+        // ---------------- march through the band chunk ----------------
+        if (kb >= 1) {
+            loadY(kb - 1);
+            storeY((kb - 1) & 1);
+        }
+        loadY(kb);
+        loadRU(kb);
+        storeY(kb & 1);
         __syncthreads();
-        uphase(k + 1, k + 1 < ke);
-        wphase(k);
+        uphase(kb, true);
+        loadY(kb + 1);
+        loadRU(kb + 1);
+        loadW(kb);
         __syncthreads();
-        yphase(k);
+        storeY((kb + 1) & 1);
         __syncthreads();
+        for (int k = kb; k < ke; ++k) {
+            const bool more = k + 1 < ke;
+            if (more) loadY(k + 2);
+            uphase(k + 1, more);
+            if (more) loadRU(k + 2);
+            wphase(k);
+            if (more) loadW(k + 1);
+            __syncthreads();
+            yphase(k);
+            __syncthreads();
+            if (more) storeY(k & 1);
+            __syncthreads();
+        }
     }
+
     du2 = block_sum<NT>(du2, red);
     u2 = block_sum<NT>(u2, red);
+    double wsum[2][3];
+    for (int f = 0; f < 2; ++f) {
+        wsum[f][0] = block_sum<NT>((double)c_hi[f], red);
+        wsum[f][1] = block_sum<NT>(s_hi[f], red);
+        wsum[f][2] = block_sum<NT>(s_all[f], red);
+    }
     if (tid == 0) {
+        a.ccount[blockIdx.x] = ncand[0];
+        a.ccount[a.grid_a + blockIdx.x] = ncand[1];
         a.part[2 * blockIdx.x] = du2;
         a.part[2 * blockIdx.x + 1] = u2;
+        for (int f = 0; f < 2; ++f)
+            for (int q = 0; q < 3; ++q)
+                a.winpart[((int64_t)f * a.grid_a + blockIdx.x) * 3 + q] = wsum[f][q];
     }
 }
 
@@ -266,51 +453,68 @@ __device__ __forceinline__ float soft(float z, double tau)
     return m > 0.0 ? copysignf((float)m, z) : 0.0f;
 }
 
-// Steps 2, 3 (soft thresholds at the selected levels), 7, 8, 13 and 14.
+// Steps 2, 3 (soft thresholds at the selected levels), 7, 8, 13 and 14; the
+// z inputs are evaluated again exactly as sweep A did.
 template <typename DT>
-__global__ __launch_bounds__(NT) void k_sweep_b(IterArgs<DT> a)
+__global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
 {
     const DevScalars *sc = a.sc;
     if (sc->stop) return;
-    __shared__ double red[NT / 64];
+    __shared__ double red[NPT / 64];
     const Dims d = a.d;
+    const int n1 = d.n1, n2 = d.n2;
     const int par = (int)(sc->iter & 1u);
     const Side<DT> src = a.side[par], dst = a.side[par ^ 1];
+    const float c4 = (float)sc->c4, d4v = (float)(sc->d4 * 0.2);
     const double ts = sc->sel[0].tau, tt = sc->sel[1].tau;
-    const int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x;
     double r2 = 0.0;
-    if (q < d.plane) {
-        const int i = (int)((q / d.n2) % d.n1);
-        const float sn = soft(a.zs[q], ts), tn = soft(a.zt[q], tt);
-        const float sp = 2.f * sn - src.s[q], tp = 2.f * tn - src.t[q];
+    const int64_t stride = (int64_t)gridDim.x * NPT;
+    for (int64_t q = (int64_t)blockIdx.x * NPT + threadIdx.x; q < d.plane; q += stride) {
+        const int i = (int)((q / n2) % n1);
+        const float vq = a.v[q];
+        const float y4 = y4_of(ld(src.y4 + q), vq, c4, d4v);
+        const float y3r = ld(src.y3 + q);
+        const float y3c = i <= n1 - 2 ? y3r : 0.f;
+        const float y3m = i >= 1 ? ld(src.y3 + q - n2) : 0.f;
+        const float so = src.s[q], to = src.t[q];
+        const float sn = soft(zs_of(so, y4), ts);
+        const float tn = soft(zt_of(to, y3m, y3c, y4), tt);
+        const float sp = 2.f * sn - so, tp = 2.f * tn - to;
         float tp1 = 0.f;
-        if (i <= d.n1 - 2) tp1 = 2.f * soft(a.zt[q + d.n2], tt) - src.t[q + d.n2];
+        if (i <= n1 - 2) {
+            const int64_t q1 = q + n2;
+            const float y4n = y4_of(ld(src.y4 + q1), a.v[q1], c4, d4v);
+            const float y3n = i + 1 <= n1 - 2 ? ld(src.y3 + q1) : 0.f;
+            const float t1 = src.t[q1];
+            tp1 = 2.f * soft(zt_of(t1, y3r, y3n, y4n), tt) - t1;
+        }
         dst.s[q] = sn;
         dst.t[q] = tn;
-        st(dst.y3 + q, ld(src.y3 + q) + kStepY * mask_le(i, d.n1) * (tp1 - tp));
-        st(dst.y4 + q, ld(a.y4p + q) + kStepY * (sp + tp));
-        const double e = 5.0 * (double)ld(dst.y4 + q) - (double)a.v[q];
-        r2 = e * e;
+        st(dst.y3 + q, y3r + kStepY * mask_le(i, n1) * (tp1 - tp));
+        const float y4new = as_stored(dst.y4, ld(a.y4p + q) + kStepY * (sp + tp));
+        st(dst.y4 + q, y4new);
+        const double e = 5.0 * (double)y4new - (double)vq;
+        r2 += e * e;
     }
-    r2 = block_sum<NT>(r2, red);
-    if (threadIdx.x == 0) a.part[2 * a.blocks_a + blockIdx.x] = r2;
+    r2 = block_sum<NPT>(r2, red);
+    if (threadIdx.x == 0) a.part[2 * a.grid_a + blockIdx.x] = r2;
 }
 
 // Fixed-order sums of the partials; l2-ball factor, stopping rule, counter.
-__global__ __launch_bounds__(NT) void k_finalize(DevScalars *sc, const double *part, int blocks_a,
+__global__ __launch_bounds__(NPT) void k_finalize(DevScalars *sc, const double *part, int grid_a,
                                                  int blocks_b)
 {
     if (sc->stop) return;
-    __shared__ double red[NT / 64];
+    __shared__ double red[NPT / 64];
     double du2 = 0.0, u2 = 0.0, r2 = 0.0;
-    for (int b = threadIdx.x; b < blocks_a; b += NT) {
+    for (int b = threadIdx.x; b < grid_a; b += NPT) {
         du2 += part[2 * b];
         u2 += part[2 * b + 1];
     }
-    for (int b = threadIdx.x; b < blocks_b; b += NT) r2 += part[2 * blocks_a + b];
-    du2 = block_sum<NT>(du2, red);
-    u2 = block_sum<NT>(u2, red);
-    r2 = block_sum<NT>(r2, red);
+    for (int b = threadIdx.x; b < blocks_b; b += NPT) r2 += part[2 * grid_a + b];
+    du2 = block_sum<NPT>(du2, red);
+    u2 = block_sum<NPT>(u2, red);
+    r2 = block_sum<NPT>(r2, red);
     if (threadIdx.x == 0) {
         const double r = sqrt(r2);
         const double rel = u2 > 0.0 ? sqrt(du2) / sqrt(u2) : __longlong_as_double(0x7ff0000000000000ll);
@@ -327,24 +531,24 @@ __global__ __launch_bounds__(NT) void k_finalize(DevScalars *sc, const double *p
 }
 
 template <typename DT>
-__global__ __launch_bounds__(NT) void k_init(Dims d, const float *v, Side<DT> s0, DevScalars *sc,
-                                             double eps, double tol)
+__global__ __launch_bounds__(NPT) void k_init(Dims d, const float *v, Side<DT> s0, DevScalars *sc,
+                                              double eps, double tol, double alpha, double beta)
 {
+    using P = typename PairOf<DT>::type;
     const int64_t N = d.plane;
-    const int64_t stride = (int64_t)gridDim.x * NT;
-    for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < N; q += stride) {
+    const int64_t stride = (int64_t)gridDim.x * NPT;
+    const float2 z2 = make_float2(0.f, 0.f);
+    for (int64_t q = (int64_t)blockIdx.x * NPT + threadIdx.x; q < N; q += stride) {
         s0.u[q] = v[q];
         s0.s[q] = 0.f;
         s0.t[q] = 0.f;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            s0.w1[c * N + q] = 0.f;
-            s0.w2[c * N + q] = 0.f;
+        for (int g = 0; g < 3; ++g) {
+            s0.w1[g * N + q] = z2;
+            s0.w2[g * N + q] = z2;
         }
-        st(s0.y1 + q, 0.f);
-        st(s0.y1 + N + q, 0.f);
-        st(s0.y2 + q, 0.f);
-        st(s0.y2 + N + q, 0.f);
+        st2((P *)s0.y1 + q, z2);
+        st2((P *)s0.y2 + q, z2);
         st(s0.y3 + q, 0.f);
         st(s0.y4 + q, 0.f);
     }
@@ -354,72 +558,99 @@ __global__ __launch_bounds__(NT) void k_init(Dims d, const float *v, Side<DT> s0
         z.d4 = 0.0;
         z.eps = eps;
         z.tol = tol;
+        z.sel[0].radius = alpha;
+        z.sel[1].radius = beta;
         *sc = z;
     }
 }
 
-__global__ void k_begin_call(DevScalars *sc, double tol)
+__global__ void k_begin_call(DevScalars *sc, double tol, double alpha, double beta)
 {
     if (threadIdx.x == 0) {
         sc->tol = tol;
         sc->calls_iter = 0u;
         sc->fallback = 0u;
+        sc->sel[0].radius = alpha;
+        sc->sel[1].radius = beta;
         if (!sc->nonfinite) sc->stop = 0u;
     }
 }
 
-// State copy in/out. var: GEO_VAR_*; planes: 1, 6 or 2.
+// State copy in/out between separate FP32 planes (the ABI layout) and the
+// workspace layout. var: GEO_VAR_*; planes: 1, 6 or 2.
 template <typename DT>
-__global__ __launch_bounds__(NT) void k_state_io(Dims d, Side<DT> s0, Side<DT> s1, DevScalars *sc,
-                                                 int var, const float *v, float *out,
-                                                 const float *in)
+__global__ __launch_bounds__(NPT) void k_state_io(Dims d, Side<DT> s0, Side<DT> s1, DevScalars *sc,
+                                                  int var, const float *v, float *out,
+                                                  const float *in)
 {
+    using P = typename PairOf<DT>::type;
     const int64_t N = d.plane;
     const int par = (int)(sc->iter & 1u);
     const Side<DT> s = par ? s1 : s0;
     const int planes = (var == GEO_VAR_W1 || var == GEO_VAR_W2) ? 6
                        : (var == GEO_VAR_Y1 || var == GEO_VAR_Y2) ? 2 : 1;
     const int64_t total = N * planes;
-    const int64_t stride = (int64_t)gridDim.x * NT;
+    const int64_t stride = (int64_t)gridDim.x * NPT;
     const float c4 = (float)sc->c4, d4v = (float)(sc->d4 * 0.2);
-    for (int64_t g = (int64_t)blockIdx.x * NT + threadIdx.x; g < total; g += stride) {
+    for (int64_t g = (int64_t)blockIdx.x * NPT + threadIdx.x; g < total; g += stride) {
+        const int pl = (int)(g / N);
+        const int64_t q = g - (int64_t)pl * N;
+        float2 *wp = var == GEO_VAR_W1 ? s.w1 : s.w2;
+        P *yp = var == GEO_VAR_Y1 ? s.y1 : s.y2;
         if (out) {
             float x = 0.f;
             switch (var) {
-            case GEO_VAR_U: x = s.u[g]; break;
-            case GEO_VAR_S: x = s.s[g]; break;
-            case GEO_VAR_T: x = s.t[g]; break;
-            case GEO_VAR_W1: x = s.w1[g]; break;
-            case GEO_VAR_W2: x = s.w2[g]; break;
-            case GEO_VAR_Y1: x = ld(s.y1 + g); break;
-            case GEO_VAR_Y2: x = ld(s.y2 + g); break;
-            case GEO_VAR_Y3: x = ld(s.y3 + g); break;
-            default: x = c4 * (ld(s.y4 + g) - d4v * v[g]); break;
+            case GEO_VAR_U: x = s.u[q]; break;
+            case GEO_VAR_S: x = s.s[q]; break;
+            case GEO_VAR_T: x = s.t[q]; break;
+            case GEO_VAR_W1:
+            case GEO_VAR_W2: {
+                const float2 w = wp[(pl >> 1) * N + q];
+                x = (pl & 1) ? w.y : w.x;
+            } break;
+            case GEO_VAR_Y1:
+            case GEO_VAR_Y2: {
+                const float2 y = ld2(yp + q);
+                x = pl ? y.y : y.x;
+            } break;
+            case GEO_VAR_Y3: x = ld(s.y3 + q); break;
+            default: x = y4_of(ld(s.y4 + q), v[q], c4, d4v); break;
             }
             out[g] = x;
         } else {
-            const float x = in[g];
             switch (var) {
-            case GEO_VAR_U: s.u[g] = x; break;
-            case GEO_VAR_S: s.s[g] = x; break;
-            case GEO_VAR_T: s.t[g] = x; break;
-            case GEO_VAR_W1: s.w1[g] = x; break;
-            case GEO_VAR_W2: s.w2[g] = x; break;
-            case GEO_VAR_Y1: st(s.y1 + g, x); break;
-            case GEO_VAR_Y2: st(s.y2 + g, x); break;
-            case GEO_VAR_Y3: st(s.y3 + g, x); break;
-            default: st(s.y4 + g, x); break;
+            case GEO_VAR_U: s.u[q] = in[q]; break;
+            case GEO_VAR_S: s.s[q] = in[q]; break;
+            case GEO_VAR_T: s.t[q] = in[q]; break;
+            case GEO_VAR_W1:
+            case GEO_VAR_W2:
+                if ((pl & 1) == 0) wp[(pl >> 1) * N + q] = make_float2(in[g], in[g + N]);
+                break;
+            case GEO_VAR_Y1:
+            case GEO_VAR_Y2:
+                if (pl == 0) st2(yp + q, make_float2(in[q], in[q + N]));
+                break;
+            case GEO_VAR_Y3: st(s.y3 + q, in[q]); break;
+            default: st(s.y4 + q, in[q]); break;
             }
         }
     }
 }
 
-// y4 loaded as-is: switch its lazy form to y4 = 1 * (stored - 0 * v/5).
-__global__ void k_y4_identity(DevScalars *sc)
+// After a state load: y4 loaded as-is switches its lazy form to
+// y4 = 1 * (stored - 0 * v/5), and the threshold predictions are dropped
+// (the loaded state does not continue the previous run).
+__global__ void k_state_loaded(DevScalars *sc, int var)
 {
     if (threadIdx.x == 0) {
-        sc->c4 = 1.0;
-        sc->d4 = 0.0;
+        if (var == GEO_VAR_Y4) {
+            sc->c4 = 1.0;
+            sc->d4 = 0.0;
+        }
+        for (int f = 0; f < 2; ++f) {
+            sc->sel[f].win_on = 0u;
+            sc->sel[f].tau_prev = 0.0;
+        }
     }
 }
 
@@ -431,10 +662,10 @@ Side<DT> side_of(void *ws, const Layout &L, int p)
     s.u = (float *)(b + L.u[p]);
     s.s = (float *)(b + L.s[p]);
     s.t = (float *)(b + L.t[p]);
-    s.w1 = (float *)(b + L.w1[p]);
-    s.w2 = (float *)(b + L.w2[p]);
-    s.y1 = (DT *)(b + L.y1[p]);
-    s.y2 = (DT *)(b + L.y2[p]);
+    s.w1 = (float2 *)(b + L.w1[p]);
+    s.w2 = (float2 *)(b + L.w2[p]);
+    s.y1 = (typename Side<DT>::P *)(b + L.y1[p]);
+    s.y2 = (typename Side<DT>::P *)(b + L.y2[p]);
     s.y3 = (DT *)(b + L.y3[p]);
     s.y4 = (DT *)(b + L.y4[p]);
     return s;
@@ -442,8 +673,27 @@ Side<DT> side_of(void *ws, const Layout &L, int p)
 
 int grid_for(int64_t n)
 {
-    int64_t b = (n + NT - 1) / NT;
+    int64_t b = (n + NPT - 1) / NPT;
     return (int)(b < 1 ? 1 : (b > 8192 ? 8192 : b));
+}
+
+// Resident blocks of sweep A on this device (queried once per process and
+// storage type).
+template <typename DT>
+int resident_grid()
+{
+    static int cached = 0;
+    if (cached == 0) {
+        int dev = 0, cus = 256, per = 2;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            hipDeviceProp_t prop;
+            if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+        }
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_a<DT>, NT, 0) != hipSuccess || per < 1)
+            per = 1;
+        cached = cus * per;
+    }
+    return cached;
 }
 
 template <typename DT>
@@ -457,12 +707,20 @@ IterArgs<DT> iter_args(const Dims &d, const float *v, void *ws, const Layout &L,
     a.side[0] = side_of<DT>(ws, L, 0);
     a.side[1] = side_of<DT>(ws, L, 1);
     a.y4p = (DT *)(b + L.y4p);
-    a.zs = (float *)(b + L.zs);
-    a.zt = (float *)(b + L.zt);
     a.sc = (DevScalars *)(b + L.scalars);
     a.part = (double *)(b + L.partials);
+    a.winpart = (double *)(b + L.winpart);
+    a.cand = (float *)(b + L.cand);
+    a.ccount = (uint32_t *)(b + L.ccount);
     a.g = sweep_grid(d.n1, d.n2, d.n3);
-    a.blocks_a = a.g.blocks();
+    const int T = a.g.blocks();
+    int G = resident_grid<DT>();
+    if (G > L.max_grid) G = L.max_grid;
+    if (G >= T) G = T;
+    else if (G >= 8) G &= ~7;
+    a.grid_a = G;
+    a.capb = (int)(L.cap / G);
+    a.blocks_b = sweep_b_blocks(d.plane);
     a.thr1 = (float)(omega * 0.25);
     a.mu_lo = (float)mu_lo;
     a.mu_hi = (float)mu_hi;
@@ -475,20 +733,28 @@ hipError_t iteration_t(const Dims &d, const float *v, void *ws, const Layout &L,
 {
     IterArgs<DT> a = iter_args<DT>(d, v, ws, L, ip.omega, ip.mu_lo, ip.mu_hi);
     Hist *hist = (Hist *)((char *)ws + L.hist);
-    const uint32_t *stop = &a.sc->stop;
-    const int blocks_b = point_blocks(d.plane);
+    ZState zs;
+    zs.d = d;
+    zs.v = v;
+    for (int p = 0; p < 2; ++p) {
+        zs.s[p] = a.side[p].s;
+        zs.t[p] = a.side[p].t;
+        zs.y3[p] = a.side[p].y3;
+        zs.y4[p] = a.side[p].y4;
+    }
+    zs.dual_bytes = L.dual_bytes;
+    zs.sc = a.sc;
     if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_sweep_a<DT>, dim3(a.blocks_a), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(k_sweep_a<DT>, dim3(a.grid_a), dim3(NT), 0, st, a);
     if (ev) (void)hipEventRecord(ev[1], st);
-    hipError_t e = select_begin(a.sc->sel, 2, ip.alpha, ip.beta, hist, stop, st);
-    if (e != hipSuccess) return e;
-    e = select_run(a.zs, a.zt, 2, d.plane, a.sc->sel, hist, stop, st);
+    hipError_t e = solver_select(zs, a.sc->sel, hist, a.winpart, a.grid_a, a.cand, a.ccount,
+                                 a.capb, &a.sc->stop, &a.sc->fallback, st);
     if (e != hipSuccess) return e;
     if (ev) (void)hipEventRecord(ev[2], st);
-    hipLaunchKernelGGL(k_sweep_b<DT>, dim3(blocks_b), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(k_sweep_b<DT>, dim3(a.blocks_b), dim3(NPT), 0, st, a);
     if (ev) (void)hipEventRecord(ev[3], st);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NT), 0, st, a.sc, (const double *)a.part,
-                       a.blocks_a, blocks_b);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NPT), 0, st, a.sc, (const double *)a.part,
+                       a.grid_a, a.blocks_b);
     if (ev) (void)hipEventRecord(ev[4], st);
     return hipGetLastError();
 }
@@ -503,22 +769,23 @@ hipError_t launch_iteration(const Dims &d, const float *v, void *ws, const Layou
 }
 
 hipError_t launch_init(const Dims &d, const float *v, void *ws, const Layout &L, double eps,
-                       double tol, hipStream_t st)
+                       double tol, double alpha, double beta, hipStream_t st)
 {
     DevScalars *sc = (DevScalars *)((char *)ws + L.scalars);
     if (L.dual_bytes == 2)
-        hipLaunchKernelGGL(k_init<bf16>, dim3(grid_for(d.plane)), dim3(NT), 0, st, d, v,
-                           side_of<bf16>(ws, L, 0), sc, eps, tol);
+        hipLaunchKernelGGL(k_init<bf16>, dim3(grid_for(d.plane)), dim3(NPT), 0, st, d, v,
+                           side_of<bf16>(ws, L, 0), sc, eps, tol, alpha, beta);
     else
-        hipLaunchKernelGGL(k_init<float>, dim3(grid_for(d.plane)), dim3(NT), 0, st, d, v,
-                           side_of<float>(ws, L, 0), sc, eps, tol);
+        hipLaunchKernelGGL(k_init<float>, dim3(grid_for(d.plane)), dim3(NPT), 0, st, d, v,
+                           side_of<float>(ws, L, 0), sc, eps, tol, alpha, beta);
     return hipGetLastError();
 }
 
-hipError_t launch_begin_call(void *ws, const Layout &L, double tol, hipStream_t st)
+hipError_t launch_begin_call(void *ws, const Layout &L, double tol, double alpha, double beta,
+                             hipStream_t st)
 {
     DevScalars *sc = (DevScalars *)((char *)ws + L.scalars);
-    hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(64), 0, st, sc, tol);
+    hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(64), 0, st, sc, tol, alpha, beta);
     return hipGetLastError();
 }
 
@@ -530,12 +797,12 @@ hipError_t launch_state_io(const Dims &d, void *ws, const Layout &L, int var, co
                        : (var == GEO_VAR_Y1 || var == GEO_VAR_Y2) ? 2 : 1;
     const int grid = grid_for(d.plane * planes);
     if (L.dual_bytes == 2)
-        hipLaunchKernelGGL(k_state_io<bf16>, dim3(grid), dim3(NT), 0, st, d, side_of<bf16>(ws, L, 0),
+        hipLaunchKernelGGL(k_state_io<bf16>, dim3(grid), dim3(NPT), 0, st, d, side_of<bf16>(ws, L, 0),
                            side_of<bf16>(ws, L, 1), sc, var, v, out, in);
     else
-        hipLaunchKernelGGL(k_state_io<float>, dim3(grid), dim3(NT), 0, st, d,
+        hipLaunchKernelGGL(k_state_io<float>, dim3(grid), dim3(NPT), 0, st, d,
                            side_of<float>(ws, L, 0), side_of<float>(ws, L, 1), sc, var, v, out, in);
-    if (in && var == GEO_VAR_Y4) hipLaunchKernelGGL(k_y4_identity, dim3(1), dim3(64), 0, st, sc);
+    if (in) hipLaunchKernelGGL(k_state_loaded, dim3(1), dim3(64), 0, st, sc, var);
     return hipGetLastError();
 }
 
