@@ -112,11 +112,12 @@ int geo_step(geo_dims dims, const geo_params *p, const float *v,
  * iteration on `stream` (instrumentation for benchmarks; the events add a
  * few microseconds per iteration). phase_ms (host, GEO_NPHASE doubles)
  * receives the summed GPU time of each phase over the call:
- *   0 sweep A  (steps 1, 4, 5, 11, 12 and the u' part of 14 fused)
+ *   0 sweep A  (steps 1, 4, 5, 11, 12 and the u' part of 14 fused, plus the
+ *              inputs of the threshold search)
  *   1 the exact soft-threshold search of the two l1-ball projections
- *   2 sweep B  (steps 2, 3, 13 and the rest of 14)
- *   3 finalize (the l2-ball factor of step 15 and the stopping rule) */
-#define GEO_NPHASE 4
+ *   2 sweep B  (steps 2, 3, 13, the rest of 14, the l2-ball factor of step
+ *              15 and the stopping rule) */
+#define GEO_NPHASE 3
 int geo_step_profiled(geo_dims dims, const geo_params *p, const float *v,
                       void *ws, size_t ws_bytes, int32_t n_iter, void *stream,
                       geo_result *out, double *phase_ms);

@@ -193,7 +193,7 @@ def geo_step(dims, p, v, ws: Workspace, n_iter: int, stream=None) -> geo_result:
     return out
 
 
-PHASES = ("sweep_a", "l1_select", "sweep_b", "finalize")
+PHASES = ("sweep_a", "l1_select", "sweep_b")
 
 
 def geo_step_profiled(dims, p, v, ws: Workspace, n_iter: int, stream=None):

@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <vector>
+
 #include "solver.hpp"
 
 namespace geo {
@@ -162,43 +164,44 @@ static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *w
     IterParams ip{p->omega, p->mu_lo, p->mu_hi, p->alpha, p->beta};
     rc = hip_status(launch_begin_call(ws, L, p->tol, p->alpha, p->beta, st));
     if (rc) return rc;
+    if (phase_ms)
+        for (int q = 0; q < GEO_NPHASE; ++q) phase_ms[q] = 0.0;
+    // Each launch slot (sweep A, search, sweep B) completes one iteration,
+    // except the slots that run the radix levels of a threshold search whose
+    // predicted window missed; the loop tops up slots until n_iter
+    // iterations are done or the stopping rule holds.
     const int every = p->check_every > 0 ? p->check_every : 32;
     DevScalars sc;
-    int launched = 0;
-    hipEvent_t *ev = nullptr;
-    if (phase_ms) {
-        for (int q = 0; q < GEO_NPHASE; ++q) phase_ms[q] = 0.0;
-        ev = new hipEvent_t[5 * (size_t)(n_iter > 0 ? n_iter : 1)];
-        for (int q = 0; q < 5 * n_iter; ++q) {
-            rc = hip_status(hipEventCreate(&ev[q]));
-            if (rc) return rc;
-        }
-    }
-    while (launched < n_iter) {
-        const int batch = (p->tol > 0.0) ? (n_iter - launched < every ? n_iter - launched : every)
-                                         : n_iter - launched;
-        for (int q = 0; q < batch; ++q) {
-            rc = hip_status(launch_iteration(d, v, ws, L, ip, st, ev ? ev + 5 * (launched + q) : nullptr));
-            if (rc) return rc;
-        }
-        launched += batch;
-        if (p->tol > 0.0 && launched < n_iter) {
-            rc = read_scalars(ws, L, &sc, st);
-            if (rc) return rc;
-            if (sc.stop) break;
-        }
-    }
-    rc = read_scalars(ws, L, &sc, st);
-    if (ev) {
-        for (int q = 0; q < launched && !rc; ++q)
-            for (int ph = 0; ph < GEO_NPHASE && !rc; ++ph) {
-                float ms = 0.f;
-                rc = hip_status(hipEventElapsedTime(&ms, ev[5 * q + ph], ev[5 * q + ph + 1]));
-                phase_ms[ph] += ms;
+    memset(&sc, 0, sizeof sc);
+    int done = 0;
+    std::vector<hipEvent_t> ev;
+    while (done < n_iter) {
+        const int remaining = n_iter - done;
+        const int batch = (p->tol > 0.0 && remaining > every) ? every : remaining;
+        if (phase_ms) {
+            const size_t need = (size_t)4 * batch;
+            while (ev.size() < need) {
+                hipEvent_t e;
+                rc = hip_status(hipEventCreate(&e));
+                if (rc) break;
+                ev.push_back(e);
             }
-        for (int q = 0; q < 5 * n_iter; ++q) (void)hipEventDestroy(ev[q]);
-        delete[] ev;
+        }
+        for (int q = 0; q < batch && !rc; ++q)
+            rc = hip_status(launch_iteration(d, v, ws, L, ip, st, phase_ms ? &ev[4 * q] : nullptr));
+        if (!rc) rc = read_scalars(ws, L, &sc, st);
+        if (!rc && phase_ms)
+            for (int q = 0; q < batch && !rc; ++q)
+                for (int ph = 0; ph < GEO_NPHASE && !rc; ++ph) {
+                    float ms = 0.f;
+                    rc = hip_status(hipEventElapsedTime(&ms, ev[4 * q + ph], ev[4 * q + ph + 1]));
+                    phase_ms[ph] += ms;
+                }
+        if (rc) break;
+        done = (int)sc.calls_iter;
+        if (sc.stop) break;
     }
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (rc) return rc;
     if (out) {
         out->iters = (int32_t)sc.calls_iter;

@@ -115,6 +115,22 @@ __device__ __forceinline__ double block_sum(double x, double *lds /* NT/64 */)
 
 namespace geo {
 
+// Radix levels of the exact l1-ball threshold search over FP32 bit patterns
+// of |z|: level 0 = bits 30..20 (2048 bins), 1 = bits 19..10, 2 = bits 9..0.
+__device__ __forceinline__ uint32_t abs_bits(float x) { return __float_as_uint(x) & 0x7fffffffu; }
+__device__ __forceinline__ uint64_t significand(uint32_t p)
+{
+    const uint32_t e = p >> 23, m = p & 0x7fffffu;
+    return e ? (uint64_t)(m | 0x800000u) : (uint64_t)m;
+}
+__device__ __forceinline__ int lvl_shift(int level) { return level == 0 ? 20 : (level == 1 ? 10 : 0); }
+__device__ __forceinline__ int lvl_bins(int level) { return level == 0 ? 2048 : 1024; }
+// exponent shared by the values of a bin of the given level
+__device__ __forceinline__ uint32_t lvl_exponent(int level, uint32_t prefix, int b)
+{
+    return level == 0 ? (uint32_t)(b >> 3) : (level == 1 ? (prefix >> 3) : (prefix >> 13));
+}
+
 // The inputs of the two l1-ball projections (steps 2 and 3 of Alg. 1) and the
 // lazily scaled y4, written with explicit rounding operations so that every
 // kernel that evaluates them (both sweeps and the fallback threshold search)

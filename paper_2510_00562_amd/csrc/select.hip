@@ -22,17 +22,6 @@ namespace {
 
 constexpr int kSelThreads = 256;
 
-__device__ __forceinline__ uint32_t abs_bits(float x) { return __float_as_uint(x) & 0x7fffffffu; }
-
-__device__ __forceinline__ uint64_t significand(uint32_t p)
-{
-    uint32_t e = p >> 23, m = p & 0x7fffffu;
-    return e ? (uint64_t)(m | 0x800000u) : (uint64_t)m;
-}
-
-// level -> (shift, bins, prefix shift)
-__device__ __forceinline__ int lvl_shift(int level) { return level == 0 ? 20 : (level == 1 ? 10 : 0); }
-__device__ __forceinline__ int lvl_bins(int level) { return level == 0 ? 2048 : 1024; }
 
 __global__ __launch_bounds__(kSelThreads) void k_select_begin(SelState *sel, int nfields, double r0,
                                                               double r1, Hist *hist,
@@ -70,31 +59,6 @@ struct ArraySrc {
     const float *z[2];
     __device__ __forceinline__ void begin() const {}
     __device__ __forceinline__ float get(int f, int64_t q) const { return z[f][q]; }
-};
-
-template <typename DT>
-struct StateSrc {
-    ZState zs;
-    int par;
-    float c4, d4v;
-    __device__ __forceinline__ void begin()
-    {
-        par = (int)(zs.sc->iter & 1u);
-        c4 = (float)zs.sc->c4;
-        d4v = (float)(zs.sc->d4 * 0.2);
-    }
-    __device__ __forceinline__ float get(int f, int64_t q) const
-    {
-        const DT *y4 = (const DT *)zs.y4[par];
-        const float y = y4_of(ld(y4 + q), zs.v[q], c4, d4v);
-        if (f == 0) return zs_of(zs.s[par][q], y);
-        const DT *y3 = (const DT *)zs.y3[par];
-        const int n1 = zs.d.n1, n2 = zs.d.n2;
-        const int i = (int)((q / n2) % n1);
-        const float y3c = i <= n1 - 2 ? ld(y3 + q) : 0.f;
-        const float y3m = i >= 1 ? ld(y3 + q - n2) : 0.f;
-        return zt_of(zs.t[par][q], y3m, y3c, y);
-    }
 };
 
 // Histogram of the pattern bits of one radix level, restricted to values
@@ -348,15 +312,130 @@ __device__ __forceinline__ double bin_value(unsigned long long msum, uint32_t fi
     return (double)msum * ldexp(1.0, (int)(e ? e : 1u) - 150);
 }
 
+// One radix level of the full search for field f (one block of kWinThreads):
+// the bins of the level are scanned in parallel from the top with exact
+// integer bin sums; the bin holding tau either finishes the search (empty,
+// one value, or single-pattern bins at level 2) or becomes the next range.
+__device__ void level_step(SelState *sel, Hist *hist, int f)
+{
+    __shared__ SelState s;
+    __shared__ double wsd[kWinThreads / 64];
+    __shared__ int best;
+    __shared__ int fin;
+    const int tid = threadIdx.x;
+    if (tid == 0) {
+        s = sel[f];
+        best = -1;
+        fin = 0;
+    }
+    __syncthreads();
+    const int level = (int)s.level;
+    const int nb = lvl_bins(level), shift = lvl_shift(level);
+    const int per = nb / kWinThreads;  // 2 or 1 bins per thread, taken from the top
+    const uint32_t base = level == 0 ? 0u : (s.prefix << (level == 1 ? 20 : 10));
+    const int btop = nb - 1 - per * tid;
+    double ts = 0.0, tc = 0.0;
+    for (int q = 0; q < per; ++q) {
+        const int b = btop - q;
+        const uint32_t e = lvl_exponent(level, s.prefix, b);
+        ts += (double)hist[f].msum[b] * ldexp(1.0, (int)(e ? e : 1u) - 150);
+        tc += (double)hist[f].count[b];
+    }
+    double allS, allC;
+    double S = s.s_above + block_exclusive_scan<double>(ts, wsd, allS);
+    double C = (double)s.c_above + block_exclusive_scan<double>(tc, wsd, allC);
+    const double radius = s.radius;
+    int mine = -1;
+    double mS = 0.0, mC = 0.0, mbs = 0.0, mbc = 0.0, mfb = 0.0;
+    for (int q = 0; q < per; ++q) {
+        const int b = btop - q;
+        const uint32_t e = lvl_exponent(level, s.prefix, b);
+        const double bs = (double)hist[f].msum[b] * ldexp(1.0, (int)(e ? e : 1u) - 150);
+        const double bc = (double)hist[f].count[b];
+        const float eb = __uint_as_float(base | ((uint32_t)b << shift));
+        const double fb = (S + bs) - (double)eb * (C + bc);
+        if (fb >= radius) {
+            mine = b;
+            mS = S;  // strictly above bin b
+            mC = C;
+            mbs = bs;
+            mbc = bc;
+            mfb = fb;
+            break;
+        }
+        S += bs;
+        C += bc;
+    }
+    if (mine >= 0) atomicMax(&best, mine);
+    __syncthreads();
+    int b = best;
+    bool owner = b >= 0 && mine == b;
+    if (b < 0 && level > 0 && tid == kWinThreads - 1) {
+        // FP64 rounding at the lower edge of a deeper range: take bin 0
+        owner = true;
+        b = 0;
+        const uint32_t e = lvl_exponent(level, s.prefix, 0);
+        mbs = (double)hist[f].msum[0] * ldexp(1.0, (int)(e ? e : 1u) - 150);
+        mbc = (double)hist[f].count[0];
+        mS = (s.s_above + allS) - mbs;
+        mC = ((double)s.c_above + allC) - mbc;
+        mfb = (mS + mbs) - (double)__uint_as_float(base) * (mC + mbc);
+    }
+    if (b < 0 && level == 0 && tid == 0) {
+        // sum |z| <= radius: inside the ball
+        SelState o = s;
+        o.tau = 0.0;
+        o.done = 1u;
+        set_window(o, true);
+        sel[f] = o;
+        fin = 1;
+    }
+    if (owner) {
+        SelState o = s;
+        const float eb = __uint_as_float(base | ((uint32_t)b << shift));
+        if (mfb == radius) {
+            o.tau = (double)eb;
+            o.done = 1u;
+        } else if (mbc == 0.0 || level == 2) {
+            o.tau = (mS - radius) / mC;
+            o.done = 1u;
+        } else if (mbc == 1.0) {
+            const double t1 = mC > 0.0 ? (mS - radius) / mC : -1.0;
+            o.tau = (mC > 0.0 && t1 >= mbs) ? t1 : (mS + mbs - radius) / (mC + 1.0);
+            o.done = 1u;
+        } else {
+            o.prefix = (level == 0 ? 0u : (s.prefix << 10)) | (uint32_t)b;
+            o.c_above = (uint64_t)mC;
+            o.s_above = mS;
+            o.level = (uint32_t)(level + 1);
+        }
+        if (o.done) set_window(o, true);
+        sel[f] = o;
+        fin = o.done ? 1 : 0;
+    }
+    __syncthreads();
+    if (!fin)  // the next level accumulates into a clean histogram
+        for (int q = tid; q < kHistBins; q += kWinThreads) {
+            hist[f].count[q] = 0u;
+            hist[f].msum[q] = 0ull;
+        }
+}
+
 __global__ __launch_bounds__(kWinThreads) void k_select_window(SelState *sel, Hist *hist,
                                                                const double *winpart, int grid_a,
                                                                const float *cand,
                                                                const uint32_t *ccount, int capb,
                                                                const uint32_t *stop,
+                                                               const uint32_t *hist_slot,
                                                                uint32_t *fallback_counter)
 {
     if (stop && *stop) return;
     const int f = blockIdx.x;
+    if (*hist_slot) {  // sweep A histogrammed a radix level of a running search
+        if (sel[f].done) return;
+        level_step(sel, hist, f);
+        return;
+    }
     __shared__ SelState s;
     __shared__ uint32_t cnt[kWinBins];
     __shared__ unsigned long long ms[kWinBins];
@@ -607,35 +686,13 @@ hipError_t select_run(const float *z0, const float *z1, int nfields, int64_t n, 
     return hipGetLastError();
 }
 
-template <typename DT>
-hipError_t solver_select_t(const ZState &zs, SelState *sel, Hist *hist, const double *winpart,
-                           int grid_a, const float *cand, const uint32_t *ccount, int capb,
-                           const uint32_t *stop, uint32_t *fallback_counter, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_select_window, dim3(2), dim3(kWinThreads), 0, st, sel, hist, winpart,
-                       grid_a, cand, ccount, capb, stop, fallback_counter);
-    StateSrc<DT> src;
-    src.zs = zs;
-    src.par = 0;
-    src.c4 = src.d4v = 0.f;
-    const int hb = hist_blocks(zs.d.plane);
-    for (int level = 0; level < 3; ++level) {
-        hipLaunchKernelGGL(k_hist<StateSrc<DT>>, dim3(hb, 2), dim3(kSelThreads), 0, st, src,
-                           zs.d.plane, (const SelState *)sel, hist, level, stop);
-        hipLaunchKernelGGL(k_select_level, dim3(2), dim3(kSelThreads), 0, st, sel, hist, level, stop);
-    }
-    return hipGetLastError();
-}
-
 hipError_t solver_select(const ZState &zs, SelState *sel, Hist *hist, const double *winpart,
                          int grid_a, const float *cand, const uint32_t *ccount, int capb,
                          const uint32_t *stop, uint32_t *fallback_counter, hipStream_t st)
 {
-    return zs.dual_bytes == 2
-               ? solver_select_t<bf16>(zs, sel, hist, winpart, grid_a, cand, ccount, capb, stop,
-                                       fallback_counter, st)
-               : solver_select_t<float>(zs, sel, hist, winpart, grid_a, cand, ccount, capb, stop,
-                                        fallback_counter, st);
+    hipLaunchKernelGGL(k_select_window, dim3(2), dim3(kWinThreads), 0, st, sel, hist, winpart,
+                       grid_a, cand, ccount, capb, stop, &zs.sc->hist_slot, fallback_counter);
+    return hipGetLastError();
 }
 
 hipError_t launch_l1_threshold(const float *x, int64_t n, double radius, SelState *sel, Hist *hist,

@@ -58,7 +58,8 @@ struct DevScalars {
     uint32_t calls_iter; // iterations done in the current geo_step call
     SelState sel[2];     // 0: s (alpha), 1: t (beta)
     uint32_t fallback;   // full radix searches in the current call
-    uint32_t pad[3];
+    uint32_t hist_slot;  // 1: sweep A of this launch slot ran a search histogram
+    uint32_t pad;
 };
 
 // Offsets (bytes) of every region of a solver workspace.
@@ -74,7 +75,10 @@ struct Layout {
 };
 
 // Tile of the fused primal/dual sweep.
-constexpr int kTI = 8, kTJ = 64, kKC = 8, kSweepThreads = 512;
+#ifndef GEO_TILE_ROWS
+#define GEO_TILE_ROWS 16
+#endif
+constexpr int kTI = GEO_TILE_ROWS, kTJ = 64, kKC = 8, kSweepThreads = kTI * kTJ;
 constexpr int kPointThreads = 256;
 constexpr int kMaxSweepGrid = 2048;  // persistent grid bound (256 CUs x 8)
 constexpr int kSweepBBlocks = 2048;  // grid-stride blocks of sweep B
@@ -126,9 +130,8 @@ hipError_t launch_init(const Dims &d, const float *v, void *ws, const Layout &L,
                        double tol, double alpha, double beta, hipStream_t st);
 hipError_t launch_begin_call(void *ws, const Layout &L, double tol, double alpha, double beta,
                              hipStream_t st);
-// ev (may be null): 5 events recorded at the phase boundaries
-// (before sweep A, after sweep A, after the threshold search, after sweep B,
-// after finalize).
+// ev (may be null): 4 events recorded at the phase boundaries (before
+// sweep A, after sweep A, after the threshold search, after sweep B).
 hipError_t launch_iteration(const Dims &d, const float *v, void *ws, const Layout &L,
                             const IterParams &ip, hipStream_t st, hipEvent_t *ev = nullptr);
 // out != null: copy the variable out (FP32); otherwise load it from in.

@@ -52,6 +52,7 @@ struct IterArgs {
     DevScalars *sc;
     double *part;    // [grid_a * 2 | blocks_b]
     double *winpart; // [2][grid_a][3]: count above, sum above, sum of |z|
+    Hist *hist;      // [2] histograms of the full threshold search
     float *cand;     // [2][grid_a][capb]: per-block slices of candidates
     uint32_t *ccount;// [2][grid_a]: candidates appended by each block
     int capb;
@@ -103,17 +104,88 @@ __device__ __forceinline__ int tile_at(int b, int G, int T, int r)
     return t < T ? t : -1;
 }
 
+// One radix level of the full threshold search over z evaluated from the
+// state (bit-identical to the sweeps' own evaluation), for every field whose
+// search is still running; LDS histograms flushed with integer atomics.
+template <typename DT>
+__device__ void search_histogram(const IterArgs<DT> &a, float *smem)
+{
+    DevScalars *sc = a.sc;
+    uint32_t *hc = reinterpret_cast<uint32_t *>(smem);                              // [2][2048]
+    unsigned long long *hm = reinterpret_cast<unsigned long long *>(smem + 2 * kHistBins);  // [2][2048]
+    for (int b = threadIdx.x; b < 2 * kHistBins; b += NT) {
+        hc[b] = 0u;
+        hm[b] = 0ull;
+    }
+    bool act[2];
+    int lvl[2];
+    uint32_t pre[2];
+    for (int f = 0; f < 2; ++f) {
+        act[f] = sc->sel[f].done == 0u;
+        lvl[f] = (int)sc->sel[f].level;
+        pre[f] = sc->sel[f].prefix;
+    }
+    __syncthreads();
+    const Dims d = a.d;
+    const int n1 = d.n1, n2 = d.n2;
+    const int par = (int)(sc->iter & 1u);
+    const Side<DT> src = a.side[par];
+    const float c4 = (float)sc->c4, d4v = (float)(sc->d4 * 0.2);
+    auto add = [&](int f, float z) {
+        const uint32_t p = abs_bits(z);
+        const int L = lvl[f], sh = lvl_shift(L);
+        if (L > 0 && (p >> (sh + 10)) != pre[f]) return;
+        const uint32_t b = (p >> sh) & (uint32_t)(lvl_bins(L) - 1);
+        atomicAdd(&hc[f * kHistBins + b], 1u);
+        atomicAdd(&hm[f * kHistBins + b], (unsigned long long)significand(p));
+    };
+    const int64_t stride = (int64_t)gridDim.x * NT;
+    for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < d.plane; q += stride) {
+        const float y4 = y4_of(ld(src.y4 + q), a.v[q], c4, d4v);
+        if (act[0]) add(0, zs_of(src.s[q], y4));
+        if (act[1]) {
+            const int i = (int)((q / n2) % n1);
+            const float y3c = i <= n1 - 2 ? ld(src.y3 + q) : 0.f;
+            const float y3m = i >= 1 ? ld(src.y3 + q - n2) : 0.f;
+            add(1, zt_of(src.t[q], y3m, y3c, y4));
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < 2 * kHistBins; b += NT) {
+        const int f = b / kHistBins, bb = b - f * kHistBins;
+        if (hc[b]) {
+            atomicAdd(&a.hist[f].count[bb], hc[b]);
+            atomicAdd((unsigned long long *)&a.hist[f].msum[bb], hm[b]);
+        }
+    }
+}
+
 template <typename DT>
 __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
 {
     using P = typename PairOf<DT>::type;
     DevScalars *sc = a.sc;
     if (sc->stop) return;
-    __shared__ float sY[2][4][S2];  // [band parity][y1v, y1h, y2v, y2h], masked
-    __shared__ float sU[2][SU];     // u' by band parity
-    __shared__ float sW[2][4][S1];  // w1', w2' planes read by neighbours: ud_h, lr_v, c_v, c_h
+    // [band parity][y1v, y1h, y2v, y2h] masked | u' by band parity |
+    // w1', w2' planes read by neighbours (ud_h, lr_v, c_v, c_h)
+    __shared__ __align__(16) float smem[2 * 4 * S2 + 2 * SU + 2 * 4 * S1];
+    float(*sY)[4][S2] = reinterpret_cast<float(*)[4][S2]>(smem);
+    float(*sU)[SU] = reinterpret_cast<float(*)[SU]>(smem + 2 * 4 * S2);
+    float(*sW)[4][S1] = reinterpret_cast<float(*)[4][S1]>(smem + 2 * 4 * S2 + 2 * SU);
     __shared__ double red[NT / 64];
     __shared__ uint32_t ncand[2];
+    static_assert(sizeof(smem) >= 2 * kHistBins * 12, "LDS holds the search histograms");
+
+    // A threshold search that missed its window runs its radix levels in the
+    // launches that follow; the sweep then only histograms z for the field(s)
+    // still searching, and the rest of the launch completes the iteration
+    // once both levels are final.
+    if (!(sc->sel[0].done && sc->sel[1].done)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) sc->hist_slot = 1u;
+        search_histogram<DT>(a, smem);
+        return;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) sc->hist_slot = 0u;
 
     const Dims d = a.d;
     const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
@@ -454,12 +526,16 @@ __device__ __forceinline__ float soft(float z, double tau)
 }
 
 // Steps 2, 3 (soft thresholds at the selected levels), 7, 8, 13 and 14; the
-// z inputs are evaluated again exactly as sweep A did.
+// z inputs are evaluated again exactly as sweep A did. A thread walks a strip
+// of RB rows of one (band, column), so the row below (needed by the D_v
+// coupling of t' and y3) is loaded once. The last block to finish also sums
+// the FP64 partials of both sweeps in a fixed order and applies the l2-ball
+// factor of step 15 and the stopping rule.
 template <typename DT>
 __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
 {
-    const DevScalars *sc = a.sc;
-    if (sc->stop) return;
+    DevScalars *sc = a.sc;
+    if (sc->stop || !(sc->sel[0].done && sc->sel[1].done)) return;
     __shared__ double red[NPT / 64];
     const Dims d = a.d;
     const int n1 = d.n1, n2 = d.n2;
@@ -468,26 +544,28 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
     const float c4 = (float)sc->c4, d4v = (float)(sc->d4 * 0.2);
     const double ts = sc->sel[0].tau, tt = sc->sel[1].tau;
     double r2 = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * NPT;
-    for (int64_t q = (int64_t)blockIdx.x * NPT + threadIdx.x; q < d.plane; q += stride) {
-        const int i = (int)((q / n2) % n1);
+    // one voxel per thread and pass; the row below (D_v coupling of y3) is
+    // re-read from cache rather than carried
+    const uint32_t N = (uint32_t)d.plane, stride = gridDim.x * NPT;
+    const uint32_t rows = (uint32_t)n1;
+    for (uint32_t q = blockIdx.x * NPT + threadIdx.x; q < N; q += stride) {
+        const int i = (int)((q / (uint32_t)n2) % rows);
         const float vq = a.v[q];
         const float y4 = y4_of(ld(src.y4 + q), vq, c4, d4v);
         const float y3r = ld(src.y3 + q);
-        const float y3c = i <= n1 - 2 ? y3r : 0.f;
         const float y3m = i >= 1 ? ld(src.y3 + q - n2) : 0.f;
         const float so = src.s[q], to = src.t[q];
-        const float sn = soft(zs_of(so, y4), ts);
-        const float tn = soft(zt_of(to, y3m, y3c, y4), tt);
-        const float sp = 2.f * sn - so, tp = 2.f * tn - to;
-        float tp1 = 0.f;
+        float y4n = 0.f, y3n = 0.f, t1 = 0.f;
         if (i <= n1 - 2) {
-            const int64_t q1 = q + n2;
-            const float y4n = y4_of(ld(src.y4 + q1), a.v[q1], c4, d4v);
-            const float y3n = i + 1 <= n1 - 2 ? ld(src.y3 + q1) : 0.f;
-            const float t1 = src.t[q1];
-            tp1 = 2.f * soft(zt_of(t1, y3r, y3n, y4n), tt) - t1;
+            const uint32_t q1 = q + (uint32_t)n2;
+            y4n = y4_of(ld(src.y4 + q1), a.v[q1], c4, d4v);
+            y3n = i + 1 <= n1 - 2 ? ld(src.y3 + q1) : 0.f;
+            t1 = src.t[q1];
         }
+        const float sn = soft(zs_of(so, y4), ts);
+        const float tn = soft(zt_of(to, y3m, i <= n1 - 2 ? y3r : 0.f, y4), tt);
+        const float sp = 2.f * sn - so, tp = 2.f * tn - to;
+        const float tp1 = i <= n1 - 2 ? 2.f * soft(zt_of(t1, y3r, y3n, y4n), tt) - t1 : 0.f;
         dst.s[q] = sn;
         dst.t[q] = tn;
         st(dst.y3 + q, y3r + kStepY * mask_le(i, n1) * (tp1 - tp));
@@ -500,11 +578,15 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
     if (threadIdx.x == 0) a.part[2 * a.grid_a + blockIdx.x] = r2;
 }
 
-// Fixed-order sums of the partials; l2-ball factor, stopping rule, counter.
+// Fixed-order sums of the block partials of both sweeps: relative change of u
+// (stopping rule), r = ||y4'/gamma4 - v|| for the lazy scale of y4 (step 15),
+// iteration counter. A separate one-block launch: a last-block-done pattern
+// inside sweep B needs a device-scope release per block, which writes back
+// the XCD's L2 each time.
 __global__ __launch_bounds__(NPT) void k_finalize(DevScalars *sc, const double *part, int grid_a,
                                                  int blocks_b)
 {
-    if (sc->stop) return;
+    if (sc->stop || !(sc->sel[0].done && sc->sel[1].done)) return;
     __shared__ double red[NPT / 64];
     double du2 = 0.0, u2 = 0.0, r2 = 0.0;
     for (int b = threadIdx.x; b < grid_a; b += NPT) {
@@ -560,6 +642,7 @@ __global__ __launch_bounds__(NPT) void k_init(Dims d, const float *v, Side<DT> s
         z.tol = tol;
         z.sel[0].radius = alpha;
         z.sel[1].radius = beta;
+        z.sel[0].done = z.sel[1].done = 1u;  // no search pending
         *sc = z;
     }
 }
@@ -650,6 +733,8 @@ __global__ void k_state_loaded(DevScalars *sc, int var)
         for (int f = 0; f < 2; ++f) {
             sc->sel[f].win_on = 0u;
             sc->sel[f].tau_prev = 0.0;
+            sc->sel[f].tau_prev2 = 0.0;
+            sc->sel[f].done = 1u;
         }
     }
 }
@@ -710,6 +795,7 @@ IterArgs<DT> iter_args(const Dims &d, const float *v, void *ws, const Layout &L,
     a.sc = (DevScalars *)(b + L.scalars);
     a.part = (double *)(b + L.partials);
     a.winpart = (double *)(b + L.winpart);
+    a.hist = (Hist *)(b + L.hist);
     a.cand = (float *)(b + L.cand);
     a.ccount = (uint32_t *)(b + L.ccount);
     a.g = sweep_grid(d.n1, d.n2, d.n3);
@@ -752,10 +838,9 @@ hipError_t iteration_t(const Dims &d, const float *v, void *ws, const Layout &L,
     if (e != hipSuccess) return e;
     if (ev) (void)hipEventRecord(ev[2], st);
     hipLaunchKernelGGL(k_sweep_b<DT>, dim3(a.blocks_b), dim3(NPT), 0, st, a);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NPT), 0, st, a.sc, (const double *)a.part, a.grid_a,
+                       a.blocks_b);
     if (ev) (void)hipEventRecord(ev[3], st);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NPT), 0, st, a.sc, (const double *)a.part,
-                       a.grid_a, a.blocks_b);
-    if (ev) (void)hipEventRecord(ev[4], st);
     return hipGetLastError();
 }
 
