@@ -24,11 +24,12 @@ ALGO_BYTES_ITER = 172  # bytes per voxel-iteration, every state word read and wr
 # Compulsory bytes per voxel of each phase: every array it reads or writes,
 # once (FP32 state and intermediates).
 PHASE_BYTES = {
-    # reads u, w1 (6), w2 (6), y1 (2), y2 (2), y4, v, s, t, y3; writes u, w1, w2,
-    # y1, y2, y4 + u'/5, z_s, z_t
-    "sweep_a": 4 * (22 + 20),
-    # reads z_s, z_t, s, t, y3, y4 + u'/5, v; writes s, t, y3, y4
-    "sweep_b": 4 * (7 + 4),
+    # reads u, w1 (6), w2 (6), y1 (2), y2 (2), y4, v (steps 1, 4, 5, 11, 12 and
+    # the u' part of 14) and s, t, y3 (inputs of the l1 projections of steps 2
+    # and 3); writes u, w1, w2, y1, y2 and y4 + u'/5
+    "sweep_a": 4 * (22 + 18),
+    # reads s, t, y3, y4, v, y4 + u'/5; writes s, t, y3, y4 (steps 2, 3, 13-15)
+    "sweep_b": 4 * (6 + 4),
 }
 
 
@@ -40,8 +41,45 @@ def parse():
     ap.add_argument("--cube", default="256x256x128", help="N1xN2xN3")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
-    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
+                                                       "sweep_a_traffic_256x256x128.txt"))
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only copy 256 MiB five times (calibration of the HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_probe():
+    """A plain device copy of known size: 256 MiB read and 256 MiB written per
+    launch. The FETCH_SIZE / WRITE_SIZE counters of this launch give the
+    factors that turn the counters of the solver's kernels into bytes."""
+    import torch
+    a = torch.empty(64 * 1024 * 1024, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print("copy probe: 5 copies of 256 MiB", flush=True)
+
+
+def read_traffic(path, cube):
+    """HBM bytes per launch of sweep A from the stored counter summary, or None
+    when it is missing, for another cube, or taken from other kernel sources."""
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as f:
+        for line in f:
+            if ":" in line and not line.startswith("#"):
+                k, v_ = line.split(":", 1)
+                kv[k.strip()] = v_.strip()
+    try:
+        if kv["cube"] != cube or kv["source_hash"] != geo_source_hash():
+            return None
+        fetch = float(kv["fetch_kib_per_dispatch"]) * float(kv["fetch_bytes_per_kib"])
+        write = float(kv["write_kib_per_dispatch"]) * float(kv["write_bytes_per_kib"])
+    except (KeyError, ValueError):
+        return None
+    return fetch + write
 
 
 def cpu_baseline(c, seconds):
@@ -70,6 +108,9 @@ def cpu_baseline(c, seconds):
 
 def main():
     args = parse()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "design is described but not built.", file=sys.stderr)
@@ -101,13 +142,7 @@ def main():
     dom = max(PHASE_BYTES, key=lambda k: phase_ms[k])
     avg_s = phase_ms[dom] / K / 1e3
     achieved = PHASE_BYTES[dom] * N / avg_s
-    traffic = None
-    if os.path.exists(args.traffic):
-        with open(args.traffic) as f:
-            tr = json.load(f)
-        ent = tr.get(dom)
-        if ent and ent.get("cube") == args.cube and ent.get("source_hash") == geo_source_hash():
-            traffic = ent["bytes_per_launch"]
+    traffic = read_traffic(args.traffic, f"{n1}x{n2}x{n3}") if dom == "sweep_a" else None
     out = {
         "metric": "P-PDS voxel-iterations/s",
         "value": value,
@@ -127,6 +162,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
                      "traffic": traffic, "bytes_per_voxel": PHASE_BYTES[dom],
+                     "traffic_bytes_per_voxel": None if traffic is None else traffic / N,
                      "avg_launch_ms": 1e3 * avg_s},
         "iteration_hbm_frac": ALGO_BYTES_ITER * value / HBM_PEAK,
         "phase_ms_per_step": {k: v_ / K for k, v_ in phase_ms.items()},

@@ -280,6 +280,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_level(SelState *sel, His
 // block prepares the full radix search (level 0) on the whole field.
 constexpr int kWinThreads = 1024;
 constexpr int kWinBins = 1024;
+constexpr int kCandLds = 28672;  // candidates staged in LDS (112 KB); more are read from HBM
 
 // Block-wide exclusive prefix sum (kWinThreads threads, fixed order, so the
 // FP64 results are deterministic). wsum: kWinThreads/64 entries of LDS.
@@ -440,6 +441,7 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(SelState *sel, Hi
     __shared__ uint32_t cnt[kWinBins];
     __shared__ unsigned long long ms[kWinBins];
     __shared__ uint32_t pre[kMaxSweepGrid];
+    __shared__ float cl[kCandLds + 64];  // staged candidates (+ one wave of slack)
     __shared__ double wsd[kWinThreads / 64];
     __shared__ uint32_t wsu[kWinThreads / 64];
     __shared__ double tot[3];
@@ -527,6 +529,21 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(SelState *sel, Hi
         nb = (int)((Pb - base) >> shift) + 1;
     }
     const int total = (int)ctot;
+    // Stage the candidates in LDS once: one wavefront per slice, each lane an
+    // asynchronous global-to-LDS load into the slice's place, so all loads
+    // are in flight together.
+    const bool staged = verdict == 0 && total <= kCandLds;
+    if (staged) {
+        const int lane = tid & 63;
+        for (int b = tid >> 6; b < grid_a; b += kWinThreads / 64) {
+            const uint32_t p0 = pre[b], p1 = b + 1 < grid_a ? pre[b + 1] : (uint32_t)total;
+            const float *src = cand + ((int64_t)f * grid_a + b) * capb;
+            for (uint32_t o = 0; o < p1 - p0; o += 64)
+                if (o + lane < p1 - p0) __builtin_amdgcn_global_load_lds(src + o + lane, cl + p0 + o, 4, 0, 0);
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
     // radix levels over the candidates
     for (int level = 0; level < 5 && verdict == 0; ++level) {
         for (int b = tid; b < kWinBins; b += kWinThreads) {
@@ -540,14 +557,18 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(SelState *sel, Hi
         // index maps to a slice by binary search over the prefix sums, so
         // every thread issues independent loads
         for (int q = tid; q < total; q += kWinThreads) {
-            int lo = 0, hi = grid_a - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pre[mid] <= (uint32_t)q) lo = mid;
-                else hi = mid - 1;
+            uint32_t p;
+            if (staged) {
+                p = __float_as_uint(cl[q]);
+            } else {
+                int lo = 0, hi = grid_a - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (pre[mid] <= (uint32_t)q) lo = mid;
+                    else hi = mid - 1;
+                }
+                p = __float_as_uint(cand[((int64_t)f * grid_a + lo) * capb + (q - (int)pre[lo])]);
             }
-            const uint32_t p =
-                __float_as_uint(cand[((int64_t)f * grid_a + lo) * capb + (q - (int)pre[lo])]);
             if (p >= base && p < lim) {
                 const uint32_t b = (p - base) >> shift;
                 atomicAdd(&cnt[b], 1u);

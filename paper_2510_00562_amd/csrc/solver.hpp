@@ -78,7 +78,13 @@ struct Layout {
 #ifndef GEO_TILE_ROWS
 #define GEO_TILE_ROWS 16
 #endif
-constexpr int kTI = GEO_TILE_ROWS, kTJ = 64, kKC = 8, kSweepThreads = kTI * kTJ;
+#ifndef GEO_BAND_CHUNK
+#define GEO_BAND_CHUNK 32
+#endif
+#ifndef GEO_SWEEP_B_ROWS
+#define GEO_SWEEP_B_ROWS 2
+#endif
+constexpr int kTI = GEO_TILE_ROWS, kTJ = 64, kKC = GEO_BAND_CHUNK, kSweepThreads = kTI * kTJ;
 constexpr int kPointThreads = 256;
 constexpr int kMaxSweepGrid = 2048;  // persistent grid bound (256 CUs x 8)
 constexpr int kSweepBBlocks = 2048;  // grid-stride blocks of sweep B

@@ -526,11 +526,11 @@ __device__ __forceinline__ float soft(float z, double tau)
 }
 
 // Steps 2, 3 (soft thresholds at the selected levels), 7, 8, 13 and 14; the
-// z inputs are evaluated again exactly as sweep A did. A thread walks a strip
-// of RB rows of one (band, column), so the row below (needed by the D_v
-// coupling of t' and y3) is loaded once. The last block to finish also sums
-// the FP64 partials of both sweeps in a fixed order and applies the l2-ball
-// factor of step 15 and the stopping rule.
+// z inputs are evaluated again exactly as sweep A did. A thread takes a strip
+// of RB rows of one (band, column) and issues all of its loads at once; only
+// the rows just above and below the strip (D_v coupling of t' and y3) are
+// read twice.
+constexpr int RB = GEO_SWEEP_B_ROWS;
 template <typename DT>
 __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
 {
@@ -538,41 +538,60 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
     if (sc->stop || !(sc->sel[0].done && sc->sel[1].done)) return;
     __shared__ double red[NPT / 64];
     const Dims d = a.d;
-    const int n1 = d.n1, n2 = d.n2;
+    const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
     const int par = (int)(sc->iter & 1u);
     const Side<DT> src = a.side[par], dst = a.side[par ^ 1];
     const float c4 = (float)sc->c4, d4v = (float)(sc->d4 * 0.2);
     const double ts = sc->sel[0].tau, tt = sc->sel[1].tau;
     double r2 = 0.0;
-    // one voxel per thread and pass; the row below (D_v coupling of y3) is
-    // re-read from cache rather than carried
-    const uint32_t N = (uint32_t)d.plane, stride = gridDim.x * NPT;
-    const uint32_t rows = (uint32_t)n1;
-    for (uint32_t q = blockIdx.x * NPT + threadIdx.x; q < N; q += stride) {
-        const int i = (int)((q / (uint32_t)n2) % rows);
-        const float vq = a.v[q];
-        const float y4 = y4_of(ld(src.y4 + q), vq, c4, d4v);
-        const float y3r = ld(src.y3 + q);
-        const float y3m = i >= 1 ? ld(src.y3 + q - n2) : 0.f;
-        const float so = src.s[q], to = src.t[q];
-        float y4n = 0.f, y3n = 0.f, t1 = 0.f;
-        if (i <= n1 - 2) {
-            const uint32_t q1 = q + (uint32_t)n2;
-            y4n = y4_of(ld(src.y4 + q1), a.v[q1], c4, d4v);
-            y3n = i + 1 <= n1 - 2 ? ld(src.y3 + q1) : 0.f;
-            t1 = src.t[q1];
+    const uint32_t nstrip = (uint32_t)((n1 + RB - 1) / RB);
+    const uint32_t items = (uint32_t)n3 * nstrip * (uint32_t)n2;
+    const uint32_t stride = gridDim.x * NPT;
+    for (uint32_t w = blockIdx.x * NPT + threadIdx.x; w < items; w += stride) {
+        const uint32_t j = w % (uint32_t)n2, rr = w / (uint32_t)n2;
+        const int ia = (int)(rr % nstrip) * RB, k = (int)(rr / nstrip);
+        const uint32_t q0 = ((uint32_t)k * (uint32_t)n1 + (uint32_t)ia) * (uint32_t)n2 + j;
+        // rows ia .. ia+RB-1 of the strip, and row ia+RB for the D_v coupling
+        float y3r[RB + 1], vq[RB + 1], y4[RB + 1], to[RB + 1], so[RB], yp[RB];
+        const float y3m0 = ia >= 1 ? ld(src.y3 + q0 - n2) : 0.f;
+#pragma unroll
+        for (int r = 0; r <= RB; ++r) {
+            const bool in = ia + r < n1;
+            const uint32_t q = q0 + (uint32_t)(r * n2);
+            y3r[r] = in ? ld(src.y3 + q) : 0.f;
+            vq[r] = in ? a.v[q] : 0.f;
+            y4[r] = in ? y4_of(ld(src.y4 + q), vq[r], c4, d4v) : 0.f;
+            to[r] = in ? src.t[q] : 0.f;
+            if (r < RB) {
+                so[r] = in ? src.s[q] : 0.f;
+                yp[r] = in ? ld(a.y4p + q) : 0.f;
+            }
         }
-        const float sn = soft(zs_of(so, y4), ts);
-        const float tn = soft(zt_of(to, y3m, i <= n1 - 2 ? y3r : 0.f, y4), tt);
-        const float sp = 2.f * sn - so, tp = 2.f * tn - to;
-        const float tp1 = i <= n1 - 2 ? 2.f * soft(zt_of(t1, y3r, y3n, y4n), tt) - t1 : 0.f;
-        dst.s[q] = sn;
-        dst.t[q] = tn;
-        st(dst.y3 + q, y3r + kStepY * mask_le(i, n1) * (tp1 - tp));
-        const float y4new = as_stored(dst.y4, ld(a.y4p + q) + kStepY * (sp + tp));
-        st(dst.y4 + q, y4new);
-        const double e = 5.0 * (double)y4new - (double)vq;
-        r2 += e * e;
+        float tp[RB + 1];
+#pragma unroll
+        for (int r = 0; r <= RB; ++r) {
+            const int i = ia + r;
+            const float y3m = r == 0 ? y3m0 : y3r[r - 1];
+            const float tn = soft(zt_of(to[r], y3m, i <= n1 - 2 ? y3r[r] : 0.f, y4[r]), tt);
+            tp[r] = 2.f * tn - to[r];
+            if (r < RB && i < n1) dst.t[q0 + (uint32_t)(r * n2)] = tn;
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int i = ia + r;
+            if (i < n1) {
+                const uint32_t q = q0 + (uint32_t)(r * n2);
+                const float sn = soft(zs_of(so[r], y4[r]), ts);
+                const float sp = 2.f * sn - so[r];
+                const float tp1 = i <= n1 - 2 ? tp[r + 1] : 0.f;
+                dst.s[q] = sn;
+                st(dst.y3 + q, y3r[r] + kStepY * mask_le(i, n1) * (tp1 - tp[r]));
+                const float y4new = as_stored(dst.y4, yp[r] + kStepY * (sp + tp[r]));
+                st(dst.y4 + q, y4new);
+                const double e = 5.0 * (double)y4new - (double)vq[r];
+                r2 += e * e;
+            }
+        }
     }
     r2 = block_sum<NPT>(r2, red);
     if (threadIdx.x == 0) a.part[2 * a.grid_a + blockIdx.x] = r2;
@@ -806,7 +825,12 @@ IterArgs<DT> iter_args(const Dims &d, const float *v, void *ws, const Layout &L,
     else if (G >= 8) G &= ~7;
     a.grid_a = G;
     a.capb = (int)(L.cap / G);
-    a.blocks_b = sweep_b_blocks(d.plane);
+    {
+        // strips of RB rows; never more blocks than the partials hold
+        const int64_t items = (int64_t)d.n3 * ((d.n1 + RB - 1) / RB) * d.n2;
+        const int nb = point_blocks(items);
+        a.blocks_b = nb < kSweepBBlocks ? nb : kSweepBBlocks;
+    }
     a.thr1 = (float)(omega * 0.25);
     a.mu_lo = (float)mu_lo;
     a.mu_hi = (float)mu_hi;
