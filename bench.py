@@ -28,8 +28,9 @@ PHASE_BYTES = {
     # the u' part of 14) and s, t, y3 (inputs of the l1 projections of steps 2
     # and 3); writes u, w1, w2, y1, y2 and y4 + u'/5
     "sweep_a": 4 * (22 + 18),
-    # reads s, t, y3, y4, v, y4 + u'/5; writes s, t, y3, y4 (steps 2, 3, 13-15)
-    "sweep_b": 4 * (6 + 4),
+    # reads s, t, y3, y4 and 5 y4 + u' - v; writes s, t, y3, y4 (steps 2, 3,
+    # 13-15; y4 is kept as the residual 5 y4' - v, so v is not needed)
+    "sweep_b": 4 * (5 + 4),
 }
 
 

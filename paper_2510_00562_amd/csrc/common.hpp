@@ -131,14 +131,13 @@ __device__ __forceinline__ uint32_t lvl_exponent(int level, uint32_t prefix, int
     return level == 0 ? (uint32_t)(b >> 3) : (level == 1 ? (prefix >> 3) : (prefix >> 13));
 }
 
-// The inputs of the two l1-ball projections (steps 2 and 3 of Alg. 1) and the
-// lazily scaled y4, written with explicit rounding operations so that every
-// kernel that evaluates them (both sweeps and the fallback threshold search)
-// gets bit-identical values.
-__device__ __forceinline__ float y4_of(float y4s, float v, float c4, float d4v)
-{
-    return __fmul_rn(c4, __fsub_rn(y4s, __fmul_rn(d4v, v)));
-}
+// The inputs of the two l1-ball projections (steps 2 and 3 of Alg. 1) and
+// y4, written with explicit rounding operations so that every kernel that
+// evaluates them (both sweeps and the fallback threshold search) gets
+// bit-identical values. y4 is stored as q = 5 y4' - v, the residual of the
+// fidelity ball before step 15 rescales it, and read as y4 = a q with a
+// device factor a (max(0, 1 - eps/||q||) / 5 after an iteration).
+__device__ __forceinline__ float y4_of(float q, float a) { return __fmul_rn(a, q); }
 __device__ __forceinline__ float zs_of(float s, float y4) { return __fsub_rn(s, y4); }
 // y3m = y3 at (i-1) (0 on the first row), y3c = y3 at i masked by m_v(i)
 __device__ __forceinline__ float zt_of(float t, float y3m, float y3c, float y4)

@@ -43,12 +43,14 @@ struct Hist {
     uint64_t msum[kHistBins];
 };
 
-// Scalars of the iteration kept on the device. y4 is stored lazily as
-// y4 = c4 * (y4s - d4 * v / 5): the fidelity-ball step of Alg. 1 (steps
-// 14-15) only rescales y4' - v/5 by max(0, 1 - eps/r), and that factor is
-// applied when y4 is next read instead of in an extra pass.
+// Scalars of the iteration kept on the device. y4 is stored as the residual
+// q = 5 y4' - v with y4 = a4 * q: the fidelity-ball step of Alg. 1 (steps
+// 14-15, eq. (23) through the conjugate prox) only rescales y4' - v/5 = q/5
+// by c4 = max(0, 1 - eps/r), r = ||q||, and that factor is applied when y4
+// is next read instead of in an extra pass. The residual form keeps y4 free
+// of the cancellation y4' - v/5 (y4' is close to v/5), also in BF16.
 struct DevScalars {
-    double c4, d4;
+    double c4, a4;  // last factor of step 15; y4 = a4 * stored
     double r;       // ||5 y4' - v|| of the last iteration
     double rel;     // ||u+ - u|| / ||u|| of the last iteration
     double eps, tol;

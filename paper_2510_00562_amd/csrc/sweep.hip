@@ -48,7 +48,7 @@ struct IterArgs {
     Dims d;
     const float *v;
     Side<DT> side[2];
-    DT *y4p;         // y4 + u'/5 (step 14, first part)
+    DT *y4p;         // 5 y4 + u' - v: step 14 before s', t', in the residual form of y4
     DevScalars *sc;
     double *part;    // [grid_a * 2 | blocks_b]
     double *winpart; // [2][grid_a][3]: count above, sum above, sum of |z|
@@ -130,7 +130,7 @@ __device__ void search_histogram(const IterArgs<DT> &a, float *smem)
     const int n1 = d.n1, n2 = d.n2;
     const int par = (int)(sc->iter & 1u);
     const Side<DT> src = a.side[par];
-    const float c4 = (float)sc->c4, d4v = (float)(sc->d4 * 0.2);
+    const float a4 = (float)sc->a4;
     auto add = [&](int f, float z) {
         const uint32_t p = abs_bits(z);
         const int L = lvl[f], sh = lvl_shift(L);
@@ -141,7 +141,7 @@ __device__ void search_histogram(const IterArgs<DT> &a, float *smem)
     };
     const int64_t stride = (int64_t)gridDim.x * NT;
     for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < d.plane; q += stride) {
-        const float y4 = y4_of(ld(src.y4 + q), a.v[q], c4, d4v);
+        const float y4 = y4_of(ld(src.y4 + q), a4);
         if (act[0]) add(0, zs_of(src.s[q], y4));
         if (act[1]) {
             const int i = (int)((q / n2) % n1);
@@ -193,7 +193,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
     if (threadIdx.x < 2) ncand[threadIdx.x] = 0u;  // published by the first barrier
     const int par = (int)(sc->iter & 1u);
     const Side<DT> src = a.side[par], dst = a.side[par ^ 1];
-    const float c4 = (float)sc->c4, d4v = (float)(sc->d4 * 0.2);
+    const float a4 = (float)sc->a4;
     const int tid = threadIdx.x;
     const int oti = tid / TJ, otj = tid % TJ;  // the thread's own point in the tile
     auto vox32 = [&](int k, int i, int j) {
@@ -265,9 +265,9 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
                 }
             }
         };
-        // u, y4 (stored), v at the own point and the u' ring point; s, t,
+        // u, y4 (stored) at the own point and the u' ring point; v, s, t,
         // y3 (row and row above) at the own point
-        float ru_u, ru_y4, ru_v, ru_s, ru_t, ru_y3c, ru_y3m, rr_u, rr_y4, rr_v;
+        float ru_u, ru_y4, ru_v, ru_s, ru_t, ru_y3c, ru_y3m, rr_u, rr_y4;
         auto loadRU = [&](int kk) {
             ru_u = ru_y4 = ru_v = ru_s = ru_t = ru_y3c = ru_y3m = 0.f;
             if (kk < n3 && own_in) {
@@ -280,13 +280,12 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
                 ru_y3c = oi <= n1 - 2 ? ld(src.y3 + q) : 0.f;
                 ru_y3m = oi >= 1 ? ld(src.y3 + q - n2) : 0.f;
             }
-            rr_u = rr_y4 = rr_v = 0.f;
+            rr_u = rr_y4 = 0.f;
             const int i = i0 + rui, j = j0 + ruj;
             if (ring_u && kk < n3 && i < n1 && j < n2) {
                 const uint32_t q = vox32(kk, i, j);
                 rr_u = src.u[q];
                 rr_y4 = ld(src.y4 + q);
-                rr_v = a.v[q];
             }
         };
         // w1, w2 (3 pairs each) at the own point and the w' ring point
@@ -311,13 +310,13 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
             return (yv[c - W2] - yv[c]) + (yh[c - 1] - yh[c]);
         };
         // u+ of step 1 and u' at one point of band kk
-        auto u_at = [&](int kk, int ui, int uj, float uo, float y4s, float vq, float &y4) {
+        auto u_at = [&](int kk, int ui, int uj, float uo, float y4s, float &y4) {
             const int buf = kk & 1;
             const int c = (ui + 2) * W2 + (uj + 2);
             float g = dT(buf, 0, c);                  // D^T y1
             if (kk <= n3 - 2) g -= dT(buf, 2, c);      // D_s^T D^T y2
             if (kk >= 1) g += dT(buf ^ 1, 2, c);
-            y4 = y4_of(y4s, vq, c4, d4v);
+            y4 = y4_of(y4s, a4);
             const float x = uo - kStepU * (g + y4);
             return x < a.mu_lo ? a.mu_lo : (x > a.mu_hi ? a.mu_hi : x);
         };
@@ -328,13 +327,14 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
             bool wr = false;
             if (kk < n3 && own_in) {
                 float y4;
-                const float un = u_at(kk, oti, otj, ru_u, ru_y4, ru_v, y4);
+                const float un = u_at(kk, oti, otj, ru_u, ru_y4, y4);
                 up = 2.f * un - ru_u;
                 if (own_band) {
                     wr = true;
                     const uint32_t q = vox32(kk, oi, oj);
                     dst.u[q] = un;
-                    st(a.y4p + q, y4 + kStepY * up);
+                    // 5 (y4 + u'/5) - v: step 14 without s', t', times 5, minus v
+                    st(a.y4p + q, (5.f * y4 + up) - ru_v);
                     const float dl = un - ru_u;
                     du2 += (double)(dl * dl);
                     u2 += (double)(ru_u * ru_u);
@@ -347,7 +347,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
                 float upr = 0.f;
                 if (kk < n3 && i0 + rui < n1 && j0 + ruj < n2) {
                     float y4;
-                    const float un = u_at(kk, rui, ruj, rr_u, rr_y4, rr_v, y4);
+                    const float un = u_at(kk, rui, ruj, rr_u, rr_y4, y4);
                     upr = 2.f * un - rr_u;
                 }
                 sU[buf][rui * WU + ruj] = upr;
@@ -541,7 +541,7 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
     const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
     const int par = (int)(sc->iter & 1u);
     const Side<DT> src = a.side[par], dst = a.side[par ^ 1];
-    const float c4 = (float)sc->c4, d4v = (float)(sc->d4 * 0.2);
+    const float a4 = (float)sc->a4;
     const double ts = sc->sel[0].tau, tt = sc->sel[1].tau;
     double r2 = 0.0;
     const uint32_t nstrip = (uint32_t)((n1 + RB - 1) / RB);
@@ -552,15 +552,14 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
         const int ia = (int)(rr % nstrip) * RB, k = (int)(rr / nstrip);
         const uint32_t q0 = ((uint32_t)k * (uint32_t)n1 + (uint32_t)ia) * (uint32_t)n2 + j;
         // rows ia .. ia+RB-1 of the strip, and row ia+RB for the D_v coupling
-        float y3r[RB + 1], vq[RB + 1], y4[RB + 1], to[RB + 1], so[RB], yp[RB];
+        float y3r[RB + 1], y4[RB + 1], to[RB + 1], so[RB], yp[RB];
         const float y3m0 = ia >= 1 ? ld(src.y3 + q0 - n2) : 0.f;
 #pragma unroll
         for (int r = 0; r <= RB; ++r) {
             const bool in = ia + r < n1;
             const uint32_t q = q0 + (uint32_t)(r * n2);
             y3r[r] = in ? ld(src.y3 + q) : 0.f;
-            vq[r] = in ? a.v[q] : 0.f;
-            y4[r] = in ? y4_of(ld(src.y4 + q), vq[r], c4, d4v) : 0.f;
+            y4[r] = in ? y4_of(ld(src.y4 + q), a4) : 0.f;
             to[r] = in ? src.t[q] : 0.f;
             if (r < RB) {
                 so[r] = in ? src.s[q] : 0.f;
@@ -586,10 +585,10 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
                 const float tp1 = i <= n1 - 2 ? tp[r + 1] : 0.f;
                 dst.s[q] = sn;
                 st(dst.y3 + q, y3r[r] + kStepY * mask_le(i, n1) * (tp1 - tp[r]));
-                const float y4new = as_stored(dst.y4, yp[r] + kStepY * (sp + tp[r]));
-                st(dst.y4 + q, y4new);
-                const double e = 5.0 * (double)y4new - (double)vq[r];
-                r2 += e * e;
+                // q+ = 5 y4' - v (step 14); r = ||q+|| (step 15)
+                const float qn = as_stored(dst.y4, yp[r] + (sp + tp[r]));
+                st(dst.y4 + q, qn);
+                r2 += (double)qn * (double)qn;
             }
         }
     }
@@ -623,7 +622,7 @@ __global__ __launch_bounds__(NPT) void k_finalize(DevScalars *sc, const double *
         sc->r = r;
         sc->rel = rel;
         sc->c4 = r > sc->eps ? 1.0 - sc->eps / r : 0.0;
-        sc->d4 = 1.0;
+        sc->a4 = 0.2 * sc->c4;
         sc->iter = sc->iter + 1u;
         sc->calls_iter = sc->calls_iter + 1u;
         if (bad) sc->nonfinite = 1u;
@@ -656,7 +655,7 @@ __global__ __launch_bounds__(NPT) void k_init(Dims d, const float *v, Side<DT> s
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         DevScalars z = {};
         z.c4 = 1.0;
-        z.d4 = 0.0;
+        z.a4 = 1.0;
         z.eps = eps;
         z.tol = tol;
         z.sel[0].radius = alpha;
@@ -693,7 +692,7 @@ __global__ __launch_bounds__(NPT) void k_state_io(Dims d, Side<DT> s0, Side<DT> 
                        : (var == GEO_VAR_Y1 || var == GEO_VAR_Y2) ? 2 : 1;
     const int64_t total = N * planes;
     const int64_t stride = (int64_t)gridDim.x * NPT;
-    const float c4 = (float)sc->c4, d4v = (float)(sc->d4 * 0.2);
+    const float a4 = (float)sc->a4;
     for (int64_t g = (int64_t)blockIdx.x * NPT + threadIdx.x; g < total; g += stride) {
         const int pl = (int)(g / N);
         const int64_t q = g - (int64_t)pl * N;
@@ -716,7 +715,7 @@ __global__ __launch_bounds__(NPT) void k_state_io(Dims d, Side<DT> s0, Side<DT> 
                 x = pl ? y.y : y.x;
             } break;
             case GEO_VAR_Y3: x = ld(s.y3 + q); break;
-            default: x = y4_of(ld(s.y4 + q), v[q], c4, d4v); break;
+            default: x = y4_of(ld(s.y4 + q), a4); break;
             }
             out[g] = x;
         } else {
@@ -739,16 +738,13 @@ __global__ __launch_bounds__(NPT) void k_state_io(Dims d, Side<DT> s0, Side<DT> 
     }
 }
 
-// After a state load: y4 loaded as-is switches its lazy form to
-// y4 = 1 * (stored - 0 * v/5), and the threshold predictions are dropped
-// (the loaded state does not continue the previous run).
+// After a state load: y4 loaded as-is is read back with the factor 1, and
+// the threshold predictions are dropped (the loaded state does not continue
+// the previous run).
 __global__ void k_state_loaded(DevScalars *sc, int var)
 {
     if (threadIdx.x == 0) {
-        if (var == GEO_VAR_Y4) {
-            sc->c4 = 1.0;
-            sc->d4 = 0.0;
-        }
+        if (var == GEO_VAR_Y4) sc->a4 = 1.0;
         for (int f = 0; f < 2; ++f) {
             sc->sel[f].win_on = 0u;
             sc->sel[f].tau_prev = 0.0;

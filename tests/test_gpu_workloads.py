@@ -1,0 +1,156 @@
+"""GPU parity at the measured workload sizes, in the launch configuration the
+benchmark times, and of the BF16 dual storage.
+
+- 256 x 256 x 128 (the benchmark cube): one iteration from a random state
+  (every state array within 1e-6 relative L2 of the FP64 oracle) and 40
+  iterations from Alg. 1's initial point, long enough to leave the full radix
+  search of the l1 thresholds for the warm-window search.
+- 512 x 512 x 224: three iterations from the initial point, FP32 state.
+- BF16 storage of the duals y1..y4 (FP32 arithmetic): one iteration from a
+  state whose duals are BF16 numbers matches the oracle to FP32 rounding on
+  the primal arrays and to one BF16 rounding on the duals; over 200
+  iterations the error against the FP64 oracle is reported and bounded
+  loosely (it is not expected to reach the FP32 bound).
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import announce, dev, f32, rel_l2
+from synth.cubes import CUBE_256x256x128, CUBE_512x512x224, SMALL_64x64x16, like, make_cube, random_state
+from test_gpu_step import STATE, compare, get_state, gpu_solver, set_state
+
+pytestmark = pytest.mark.gpu
+
+DUALS = ("y1", "y2", "y3", "y4")
+PRIMAL = ("u", "s", "t", "w1", "w2")
+
+
+def bf16(a):
+    """Round float64 values to the nearest BF16 number (ties to even), via
+    the FP32 bit pattern: the rounding the BF16 storage applies."""
+    x = np.asarray(a, dtype=np.float32)
+    b = x.view(np.uint32).astype(np.uint64)
+    r = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def test_bf16_rounding_helper():
+    # 1 + 2^-8 is halfway between BF16 neighbours 1 and 1 + 2^-7: ties to even
+    assert bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0
+    assert bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+    assert bf16(np.array([-0.1]))[0] == -0.10009765625
+
+
+def test_benchmark_cube_one_step_from_random_state(ora):
+    shape = CUBE_256x256x128.n3, CUBE_256x256x128.n1, CUBE_256x256x128.n2
+    announce(f"benchmark cube {shape}: one step from a random state")
+    c = make_cube(CUBE_256x256x128)
+    v = f32(c["v"])
+    st = {k: f32(x) for k, x in random_state(shape, 21).items()}
+    N = v.size
+    prm = dict(eps=0.5 * np.sqrt(N) * 0.1, alpha=0.3 * 0.1 * N, beta=0.2 * 0.1 * N, omega=0.03)
+    geo, dims, p, ws, vd = gpu_solver(shape, v, prm)
+    set_state(geo, dims, p, ws, vd, st)
+    res = geo.geo_step(dims, p, vd, ws, 1)
+    S = ora.Solver(v, prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"], state=st)
+    S.step(1)
+    compare(get_state(geo, dims, p, ws, vd, shape), S.state, 1e-6)
+    rel, r, ts, tt = S.trace[-1]
+    assert res.r == pytest.approx(r, rel=1e-6)
+    assert res.tau_s == pytest.approx(ts, rel=1e-6)
+    assert res.tau_t == pytest.approx(tt, rel=1e-6)
+
+
+def test_benchmark_cube_40_iterations(ora):
+    c = make_cube(CUBE_256x256x128)
+    v = f32(c["v"])
+    announce(f"benchmark cube {v.shape}: 40 iterations from the initial point")
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=c["omega"])
+    geo, dims, p, ws, vd = gpu_solver(v.shape, v, prm)
+    res = geo.geo_step(dims, p, vd, ws, 40)
+    assert res.iters == 40
+    g = get_state(geo, dims, p, ws, vd, v.shape)
+    S = ora.Solver(v, prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"])
+    S.step(40)
+    errs = {n: rel_l2(g[n], S.state[n]) for n in STATE}
+    print("rel L2 after 40 iterations:", {k: f"{e:.2e}" for k, e in errs.items()}, flush=True)
+    assert errs["u"] <= 1e-5
+    assert max(errs.values()) <= 1e-4
+    rel, r, ts, tt = S.trace[-1]
+    assert res.tau_s == pytest.approx(ts, rel=1e-5)
+    assert res.tau_t == pytest.approx(tt, rel=1e-5)
+    assert res.r == pytest.approx(r, rel=1e-6)
+
+
+def test_large_cube_three_iterations(ora):
+    c = make_cube(CUBE_512x512x224)
+    v = f32(c["v"])
+    announce(f"large cube {v.shape}: 3 iterations from the initial point")
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=c["omega"])
+    geo, dims, p, ws, vd = gpu_solver(v.shape, v, prm)
+    geo.geo_step(dims, p, vd, ws, 3)
+    g = get_state(geo, dims, p, ws, vd, v.shape)
+    del ws
+    S = ora.Solver(v, prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"])
+    S.step(3)
+    compare(g, S.state, 1e-5)
+
+
+@pytest.mark.parametrize("shape", [(17, 9, 130), (33, 20, 64)])
+def test_bf16_duals_one_step(ora, shape):
+    announce(f"BF16 duals, one step from a random state {shape}")
+    n3, n1, n2 = shape
+    c = make_cube(like(SMALL_64x64x16, n1=n1, n2=n2, n3=n3, seed=5, cells=5))
+    v = f32(c["v"])
+    st = {k: f32(x) for k, x in random_state(shape, 8).items()}
+    for n in DUALS:
+        st[n] = bf16(st[n])
+    N = v.size
+    prm = dict(eps=0.5 * np.sqrt(N) * 0.1, alpha=0.3 * 0.1 * N, beta=0.2 * 0.1 * N, omega=0.05)
+    geo, dims, p, ws, vd = gpu_solver(shape, v, prm, dual_storage=1)
+    set_state(geo, dims, p, ws, vd, st)
+    res = geo.geo_step(dims, p, vd, ws, 1)
+    g = get_state(geo, dims, p, ws, vd, shape)
+    S = ora.Solver(v, prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"], state=st)
+    S.step(1)
+    compare(g, S.state, 1e-6, names=PRIMAL)
+    # the stored duals are the oracle's rounded once to BF16; where the FP32
+    # arithmetic (errors relative to the operands, not to a result that
+    # cancels) lands next to a rounding boundary the other neighbour, one
+    # BF16 unit away, is as good
+    for n in ("y1", "y2", "y3"):
+        ora_n = S.state[n]
+        ref = bf16(ora_n)
+        assert np.mean(g[n] == ref) >= 0.99, n
+        tol = 2.0 ** -7 * np.abs(ora_n) + 1e-6 * np.abs(ora_n).max()
+        assert np.all(np.abs(g[n] - ref) <= tol), n
+    # y4 comes back as (c/5) q with q = 5 y4' - v stored in BF16
+    assert rel_l2(g["y4"], S.state["y4"]) <= 2.0 ** -8
+    rel, r, ts, tt = S.trace[-1]
+    assert res.tau_s == pytest.approx(ts, rel=1e-6)
+    assert res.tau_t == pytest.approx(tt, rel=1e-6)
+    assert res.r == pytest.approx(r, rel=2.0 ** -8)
+
+
+def test_bf16_duals_200_iterations(ora):
+    """Error of the BF16 dual storage against the FP64 oracle after 200
+    iterations on the 64 x 64 x 16 cube (reported; bounded loosely)."""
+    announce("BF16 duals, 64x64x16, 200 iterations")
+    c = make_cube(SMALL_64x64x16)
+    v = f32(c["v"])
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=0.03)
+    out = {}
+    for mode in (0, 1):
+        geo, dims, p, ws, vd = gpu_solver(v.shape, v, prm, dual_storage=mode)
+        geo.geo_step(dims, p, vd, ws, 200)
+        out[mode] = get_state(geo, dims, p, ws, vd, v.shape)["u"]
+    S = ora.Solver(v, prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"])
+    S.step(200)
+    e32, e16 = rel_l2(out[0], S.u), rel_l2(out[1], S.u)
+    m_ora = ora.mpsnr(S.u, c["u_clean"])
+    gap16 = abs(ora.mpsnr(out[1], c["u_clean"]) - m_ora)
+    print(f"u rel L2 vs oracle: FP32 {e32:.2e}, BF16 duals {e16:.2e}; "
+          f"MPSNR oracle {m_ora:.3f} dB, BF16 gap {gap16:.4f} dB", flush=True)
+    assert e32 <= 1e-4
+    assert e16 <= 1e-2
+    assert gap16 <= 0.1
