@@ -74,6 +74,11 @@ typedef struct {
                             flag (0 = 32); the count returned is exact
                             whatever this is, since the device stops
                             iterating on its own once the rule is met      */
+    int32_t band_chunk;  /* bands each tile of the fused sweep marches
+                            through (0 = 32; values below 8 count as 8; raised
+                            when a cube would have more than 4096 tiles). A
+                            performance knob only: results do not depend on
+                            it beyond FP64 summation order.               */
 } geo_params;
 
 typedef struct {
@@ -127,6 +132,29 @@ int geo_solve(geo_dims dims, const geo_params *p, const float *v,
               float *u, float *s, float *t, void *ws, size_t ws_bytes,
               void *stream, geo_result *out);
 
+/* Batched iterations: n_cubes independent solver states (cubes of any sizes,
+ * each initialised by geo_state_init in its own workspace) advanced together,
+ * one launch sequence per iteration for all of them: the fused sweep runs
+ * persistently over the concatenated tiles of every cube, the threshold
+ * search and the finalisation take one block per cube and field. Each cube
+ * does n_iter iterations of Alg. 1 or stops earlier by its own rule (eq.
+ * (28), its p[c].tol); a cube that is done idles while the others go on, so
+ * every cube's iterates are exactly those geo_step would give it alone.
+ *   dims, p, v, ws, ws_bytes, out: HOST arrays of n_cubes entries (v[c] and
+ *       ws[c] are device pointers); every p[c].dual_storage must be equal.
+ *   table: device buffer of geo_batch_table_size bytes (256-byte aligned)
+ *       for the launch table; it may be reused by later calls.
+ *   use_graph != 0: one iteration's launch sequence is captured once into a
+ *       HIP graph and replayed (fewer launches on the host).
+ * Blocking; returns GEO_ENONFINITE if any cube saw NaN/Inf, else GEO_MAXITER
+ * if any cube with tol > 0 did not meet its rule, else GEO_OK. 1 <= n_cubes
+ * <= 64. */
+int geo_batch_table_size(int32_t n_cubes, size_t *bytes);
+int geo_batch_step(int32_t n_cubes, const geo_dims *dims, const geo_params *p,
+                   const float *const *v, void *const *ws, const size_t *ws_bytes,
+                   void *table, size_t table_bytes, int32_t n_iter, int32_t use_graph,
+                   void *stream, geo_result *out);
+
 /* State variables, for parity tests, checkpointing and resume. */
 enum {
     GEO_VAR_U = 0, GEO_VAR_S, GEO_VAR_T, GEO_VAR_W1, GEO_VAR_W2,
@@ -136,8 +164,8 @@ enum {
 /* Copy a state variable out of / into the workspace in FP32 (planes as
  * above: 1 for u, s, t, y3, y4; 6 for w1, w2; 2 for y1, y2). p gives the
  * storage type of the workspace. Loading any state is allowed, including
- * entries the operators never read. v is needed to read y4 (the workspace
- * keeps y4 in a scaled form). Asynchronous. */
+ * entries the operators never read. v may be NULL (the workspace keeps y4
+ * in a scaled residual form that does not need it). Asynchronous. */
 int geo_state_get(geo_dims dims, const geo_params *p, const void *ws, size_t ws_bytes,
                   int32_t var, const float *v, float *out, void *stream);
 int geo_state_set(geo_dims dims, const geo_params *p, void *ws, size_t ws_bytes,

@@ -43,7 +43,7 @@ class geo_params(ctypes.Structure):
                 ("mu_lo", ctypes.c_double), ("mu_hi", ctypes.c_double),
                 ("omega", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("dual_storage", ctypes.c_int32),
-                ("check_every", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("band_chunk", ctypes.c_int32)]
 
 
 class geo_result(ctypes.Structure):
@@ -98,6 +98,10 @@ def lib():
             "geo_prox_l12": [_vp, _vp, i64, d, _vp, _vp, _vp],
             "geo_project_box": [_vp, i64, d, d, _vp, _vp],
             "geo_strerror": [ctypes.c_int],
+            "geo_batch_table_size": [i32, ctypes.POINTER(_sz)],
+            "geo_batch_step": [i32, ctypes.POINTER(geo_dims), P, ctypes.POINTER(_vp),
+                               ctypes.POINTER(_vp), ctypes.POINTER(_sz), _vp, _sz, i32, i32, _vp,
+                               R],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -147,9 +151,9 @@ def dims_of(shape) -> geo_dims:
 
 
 def params(eps, alpha, beta, mu_lo=0.0, mu_hi=1.0, omega=0.03, max_iter=1000, tol=0.0,
-           dual_storage=GEO_STORE_F32, check_every=0) -> geo_params:
+           dual_storage=GEO_STORE_F32, check_every=0, band_chunk=0) -> geo_params:
     return geo_params(eps, alpha, beta, mu_lo, mu_hi, omega, max_iter, tol, dual_storage,
-                      check_every)
+                      check_every, band_chunk)
 
 
 def _check(rc, where, allow_maxiter=False):
@@ -213,6 +217,33 @@ def geo_solve(dims, p, v, u, s, t, ws: Workspace, stream=None) -> geo_result:
                            ws.nbytes, _stream(stream), ctypes.byref(out)), "geo_solve",
            allow_maxiter=True)
     return out
+
+
+def geo_batch_table_size(n_cubes: int) -> int:
+    n = _sz()
+    _check(lib().geo_batch_table_size(int(n_cubes), ctypes.byref(n)), "geo_batch_table_size")
+    return n.value
+
+
+def geo_batch_step(dims, ps, vs, wss, table: Workspace, n_iter: int, use_graph=False,
+                   stream=None):
+    """n_iter iterations of every cube of a batch in one launch sequence per
+    iteration. dims, ps, vs, wss: lists (geo_dims, geo_params, device cube,
+    Workspace) of equal length; table: a Workspace of geo_batch_table_size
+    bytes. Returns (status, [geo_result per cube])."""
+    n = len(dims)
+    if not (len(ps) == len(vs) == len(wss) == n):
+        raise ValueError("dims, ps, vs and wss must have one entry per cube")
+    D = (geo_dims * n)(*dims)
+    Pa = (geo_params * n)(*ps)
+    V = (_vp * n)(*[_f32(v) for v in vs])
+    W = (_vp * n)(*[w.ptr for w in wss])
+    B = (_sz * n)(*[w.nbytes for w in wss])
+    out = (geo_result * n)()
+    rc = _check(lib().geo_batch_step(n, D, Pa, V, W, B, table.ptr, table.nbytes, int(n_iter),
+                                     1 if use_graph else 0, _stream(stream), out),
+                "geo_batch_step", allow_maxiter=True)
+    return rc, list(out)
 
 
 def geo_state_get(dims, p, ws: Workspace, var: str, v, out, stream=None):

@@ -21,8 +21,8 @@ Layout make_layout(int n1, int n2, int n3, int dual_storage)
     const int db = dual_storage == GEO_STORE_BF16 ? 2 : 4;
     const size_t fd = N * db;
     L.dual_bytes = db;
-    L.max_grid = sweep_a_max_grid(n1, n2, n3);
-    L.n_part = 2 * L.max_grid + sweep_b_blocks((int64_t)N);
+    L.max_tiles = max_tiles(n1, n2, n3);
+    L.n_part = 2 * L.max_tiles + sweep_b_blocks((int64_t)N);
     L.cap = (int64_t)N / 16 > 65536 ? (int64_t)N / 16 : 65536;
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -34,9 +34,10 @@ Layout make_layout(int n1, int n2, int n3, int dual_storage)
     L.partials = take(sizeof(double) * (size_t)L.n_part);
     L.hist = take(2 * sizeof(Hist));
     L.y4p = take(fd);
-    L.winpart = take(sizeof(double) * 2 * 3 * (size_t)L.max_grid);
+    L.winpart = take(sizeof(double) * 2 * 3 * (size_t)L.max_tiles);
     L.cand = take(sizeof(float) * 2 * (size_t)L.cap);
-    L.ccount = take(sizeof(uint32_t) * 2 * (size_t)L.max_grid);
+    L.ccount = take(sizeof(uint32_t) * 2 * (size_t)L.max_tiles);
+    L.table = take(sizeof(CubeEntry));
     for (int p = 0; p < 2; ++p) {
         L.u[p] = take(f4);
         L.s[p] = take(f4);
@@ -85,6 +86,7 @@ bool params_ok(const geo_params *p)
     if (isnan(p->tol)) return false;
     if (p->dual_storage != GEO_STORE_F32 && p->dual_storage != GEO_STORE_BF16) return false;
     if (p->check_every < 0) return false;
+    if (p->band_chunk < 0) return false;
     return true;
 }
 
@@ -152,44 +154,90 @@ int geo_state_init(geo_dims dims, const geo_params *p, const float *v, void *ws,
                                   S(stream)));
 }
 
-static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
-                     int32_t n_iter, void *stream, geo_result *out, double *phase_ms)
+// One solver call over n cubes (n = 1: the single-cube entry points). The
+// launch table (host image `ent`, device copy at `table`) is written once;
+// each launch slot (sweep A, search, sweep B, finalize) completes one
+// iteration of every busy cube, except the slots in which a cube runs the
+// radix levels of a threshold search whose predicted window missed. The
+// loop tops up slots until every cube has done n_iter iterations (the device
+// idles a cube after them) or met its stopping rule.
+static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const float *const *v,
+                     void *const *ws, const size_t *ws_bytes, void *table, size_t table_bytes,
+                     int32_t n_iter, int use_graph, hipStream_t st, geo_result *out,
+                     double *phase_ms)
 {
-    if (!dims_ok(dims) || !params_ok(p) || !v || n_iter < 0) return GEO_EINVAL;
-    Layout L;
-    int rc = check_ws(dims, p, ws, ws_bytes, &L);
-    if (rc) return rc;
-    const hipStream_t st = S(stream);
-    const Dims d = to_dims(dims);
-    IterParams ip{p->omega, p->mu_lo, p->mu_hi, p->alpha, p->beta};
-    rc = hip_status(launch_begin_call(ws, L, p->tol, p->alpha, p->beta, st));
+    if (n < 1 || n > kMaxBatch || !dims || !p || !v || !ws || !ws_bytes || n_iter < 0)
+        return GEO_EINVAL;
+    std::vector<Layout> L(n);
+    for (int c = 0; c < n; ++c) {
+        if (!dims_ok(dims[c]) || !params_ok(&p[c]) || !v[c]) return GEO_EINVAL;
+        if (p[c].dual_storage != p[0].dual_storage) return GEO_EINVAL;
+        int rc = check_ws(dims[c], &p[c], ws[c], ws_bytes[c], &L[c]);
+        if (rc) return rc;
+    }
+    if (!table || ((uintptr_t)table & 255u) || table_bytes < (size_t)n * sizeof(CubeEntry))
+        return GEO_EWORKSPACE;
+    std::vector<CubeEntry> ent(n);
+    LaunchShape sh{n, 0, 0, 0};
+    for (int c = 0; c < n; ++c) {
+        int nt = 0, nb = 0;
+        cube_entry(&ent[c], to_dims(dims[c]), v[c], ws[c], L[c], p[c].omega, p[c].mu_lo, p[c].mu_hi,
+                   p[c].band_chunk, sh.total_tiles, sh.total_b, &nt, &nb);
+        sh.total_tiles += nt;
+        sh.total_b += nb;
+    }
+    sh.grid_a = sweep_a_grid(L[0].dual_bytes, sh.total_tiles);
+    int rc = hip_status(hipMemcpyAsync(table, ent.data(), (size_t)n * sizeof(CubeEntry),
+                                       hipMemcpyHostToDevice, st));
+    for (int c = 0; c < n && !rc; ++c)
+        rc = hip_status(launch_begin_call(ws[c], L[c], p[c].tol, p[c].alpha, p[c].beta, n_iter, st));
     if (rc) return rc;
     if (phase_ms)
         for (int q = 0; q < GEO_NPHASE; ++q) phase_ms[q] = 0.0;
-    // Each launch slot (sweep A, search, sweep B) completes one iteration,
-    // except the slots that run the radix levels of a threshold search whose
-    // predicted window missed; the loop tops up slots until n_iter
-    // iterations are done or the stopping rule holds.
-    const int every = p->check_every > 0 ? p->check_every : 32;
-    DevScalars sc;
-    memset(&sc, 0, sizeof sc);
-    int done = 0;
+    bool any_tol = false;
+    for (int c = 0; c < n; ++c) any_tol = any_tol || p[c].tol > 0.0;
+    const int every = p[0].check_every > 0 ? p[0].check_every : 32;
+
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    if (use_graph && !phase_ms) {
+        // one slot captured on a private stream (capture needs a non-null
+        // stream), replayed on the caller's
+        hipStream_t cs = nullptr;
+        rc = hip_status(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        if (!rc) rc = hip_status(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        if (!rc) {
+            hipError_t le = launch_slot(table, L[0].dual_bytes, sh, cs, nullptr);
+            hipError_t ee = hipStreamEndCapture(cs, &graph);
+            rc = hip_status(le != hipSuccess ? le : ee);
+        }
+        if (!rc) rc = hip_status(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+        if (cs) (void)hipStreamDestroy(cs);
+    }
+
+    std::vector<DevScalars> sc(n);
     std::vector<hipEvent_t> ev;
-    while (done < n_iter) {
-        const int remaining = n_iter - done;
-        const int batch = (p->tol > 0.0 && remaining > every) ? every : remaining;
+    int behind = n_iter;  // slots still needed by the furthest-behind busy cube
+    while (!rc) {
+        const int batch = (any_tol && behind > every) ? every : behind;
         if (phase_ms) {
             const size_t need = (size_t)4 * batch;
-            while (ev.size() < need) {
+            while (ev.size() < need && !rc) {
                 hipEvent_t e;
                 rc = hip_status(hipEventCreate(&e));
-                if (rc) break;
-                ev.push_back(e);
+                if (!rc) ev.push_back(e);
             }
         }
-        for (int q = 0; q < batch && !rc; ++q)
-            rc = hip_status(launch_iteration(d, v, ws, L, ip, st, phase_ms ? &ev[4 * q] : nullptr));
-        if (!rc) rc = read_scalars(ws, L, &sc, st);
+        for (int q = 0; q < batch && !rc; ++q) {
+            if (gexec)
+                rc = hip_status(hipGraphLaunch(gexec, st));
+            else
+                rc = hip_status(launch_slot(table, L[0].dual_bytes, sh, st, phase_ms ? &ev[4 * q] : nullptr));
+        }
+        for (int c = 0; c < n && !rc; ++c)
+            rc = hip_status(hipMemcpyAsync(&sc[c], (const char *)ws[c] + L[c].scalars, sizeof(DevScalars),
+                                           hipMemcpyDeviceToHost, st));
+        if (!rc) rc = hip_status(hipStreamSynchronize(st));
         if (!rc && phase_ms)
             for (int q = 0; q < batch && !rc; ++q)
                 for (int ph = 0; ph < GEO_NPHASE && !rc; ++ph) {
@@ -197,27 +245,49 @@ static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *w
                     rc = hip_status(hipEventElapsedTime(&ms, ev[4 * q + ph], ev[4 * q + ph + 1]));
                     phase_ms[ph] += ms;
                 }
-        if (rc) break;
-        done = (int)sc.calls_iter;
-        if (sc.stop) break;
+        behind = 0;
+        for (int c = 0; c < n; ++c) {
+            const int left = sc[c].stop ? 0 : n_iter - (int)sc[c].calls_iter;
+            if (left > behind) behind = left;
+        }
+        if (batch == 0 || behind <= 0) break;
     }
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
     if (rc) return rc;
-    if (out) {
-        out->iters = (int32_t)sc.calls_iter;
-        out->converged = (p->tol > 0.0 && sc.stop && !sc.nonfinite) ? 1 : 0;
-        out->rel_change = sc.rel;
-        out->r = sc.r;
-        out->tau_s = sc.sel[0].tau;
-        out->tau_t = sc.sel[1].tau;
-        out->total_iters = (int32_t)sc.iter;
-        out->fallback_passes = (int32_t)sc.fallback;
-        out->cand_s = (int32_t)sc.sel[0].cand_count;
-        out->cand_t = (int32_t)sc.sel[1].cand_count;
+    int status = GEO_OK;
+    for (int c = 0; c < n; ++c) {
+        const DevScalars &x = sc[c];
+        if (out) {
+            geo_result &o = out[c];
+            o.iters = (int32_t)x.calls_iter;
+            o.converged = (p[c].tol > 0.0 && x.stop && !x.nonfinite) ? 1 : 0;
+            o.rel_change = x.rel;
+            o.r = x.r;
+            o.tau_s = x.sel[0].tau;
+            o.tau_t = x.sel[1].tau;
+            o.total_iters = (int32_t)x.iter;
+            o.fallback_passes = (int32_t)x.fallback;
+            o.cand_s = (int32_t)x.sel[0].cand_count;
+            o.cand_t = (int32_t)x.sel[1].cand_count;
+        }
+        if (x.nonfinite) status = GEO_ENONFINITE;
+        else if (status == GEO_OK && p[c].tol > 0.0 && !x.stop) status = GEO_MAXITER;
     }
-    if (sc.nonfinite) return GEO_ENONFINITE;
-    if (p->tol > 0.0 && !sc.stop) return GEO_MAXITER;
-    return GEO_OK;
+    return status;
+}
+
+static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
+                     int32_t n_iter, void *stream, geo_result *out, double *phase_ms)
+{
+    if (!dims_ok(dims) || !params_ok(p) || !v || n_iter < 0) return GEO_EINVAL;
+    Layout L;
+    int rc = check_ws(dims, p, ws, ws_bytes, &L);
+    if (rc) return rc;
+    void *table = (char *)ws + L.table;
+    return run_cubes(1, &dims, p, &v, &ws, &ws_bytes, table, sizeof(CubeEntry), n_iter, 0, S(stream),
+                     out, phase_ms);
 }
 
 int geo_step(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
@@ -251,13 +321,28 @@ int geo_solve(geo_dims dims, const geo_params *p, const float *v, float *u, floa
     return rc ? rc : step_rc;
 }
 
+int geo_batch_table_size(int32_t n_cubes, size_t *bytes)
+{
+    if (n_cubes < 1 || n_cubes > kMaxBatch || !bytes) return GEO_EINVAL;
+    *bytes = align256((size_t)n_cubes * sizeof(CubeEntry));
+    return GEO_OK;
+}
+
+int geo_batch_step(int32_t n_cubes, const geo_dims *dims, const geo_params *p,
+                   const float *const *v, void *const *ws, const size_t *ws_bytes, void *table,
+                   size_t table_bytes, int32_t n_iter, int32_t use_graph, void *stream,
+                   geo_result *out)
+{
+    return run_cubes(n_cubes, dims, p, v, ws, ws_bytes, table, table_bytes, n_iter, use_graph ? 1 : 0,
+                     S(stream), out, nullptr);
+}
+
 static int state_io(geo_dims dims, const void *ws, size_t ws_bytes, int32_t var, const float *v,
                     float *out, const float *in, int dual_storage, void *stream)
 {
     if (!dims_ok(dims) || var < GEO_VAR_U || var > GEO_VAR_Y4) return GEO_EINVAL;
     if (dual_storage != GEO_STORE_F32 && dual_storage != GEO_STORE_BF16) return GEO_EINVAL;
     if ((out == nullptr) == (in == nullptr)) return GEO_EINVAL;
-    if (var == GEO_VAR_Y4 && !v && out) return GEO_EINVAL;
     geo_params p;
     memset(&p, 0, sizeof p);
     p.dual_storage = dual_storage;

@@ -422,25 +422,30 @@ __device__ void level_step(SelState *sel, Hist *hist, int f)
         }
 }
 
-__global__ __launch_bounds__(kWinThreads) void k_select_window(SelState *sel, Hist *hist,
-                                                               const double *winpart, int grid_a,
-                                                               const float *cand,
-                                                               const uint32_t *ccount, int capb,
-                                                               const uint32_t *stop,
-                                                               const uint32_t *hist_slot,
-                                                               uint32_t *fallback_counter)
+// One block per (cube, field) of a launch table: block 2c + f.
+__global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table, int stride)
 {
-    if (stop && *stop) return;
-    const int f = blockIdx.x;
-    if (*hist_slot) {  // sweep A histogrammed a radix level of a running search
+    const CubeCommon &cc = *reinterpret_cast<const CubeCommon *>(table + (size_t)(blockIdx.x >> 1) * stride);
+    const int f = blockIdx.x & 1;
+    DevScalars *sc = cc.sc;
+    if (idle(sc)) return;
+    SelState *sel = sc->sel;
+    Hist *hist = cc.hist;
+    if (sc->hist_slot) {  // sweep A histogrammed a radix level of a running search
         if (sel[f].done) return;
         level_step(sel, hist, f);
         return;
     }
+    const double *winpart = cc.winpart;
+    const int grid_a = cc.ntiles;  // candidate slices: one per tile
+    const float *cand = cc.cand;
+    const uint32_t *ccount = cc.ccount;
+    const int capb = cc.capt;
+    uint32_t *fallback_counter = &sc->fallback;
     __shared__ SelState s;
     __shared__ uint32_t cnt[kWinBins];
     __shared__ unsigned long long ms[kWinBins];
-    __shared__ uint32_t pre[kMaxSweepGrid];
+    __shared__ uint32_t pre[kMaxTiles];
     __shared__ float cl[kCandLds + 64];  // staged candidates (+ one wave of slack)
     __shared__ double wsd[kWinThreads / 64];
     __shared__ uint32_t wsu[kWinThreads / 64];
@@ -472,14 +477,15 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(SelState *sel, Hi
     }
     // block partials of sweep A (fixed order) and the candidate slices
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    uint32_t mine = 0u;  // this thread's slice counts (grid_a <= 2 * kWinThreads)
+    uint32_t mine = 0u;  // this thread's slice counts (per consecutive slices)
+    const int per = (grid_a + kWinThreads - 1) / kWinThreads;
     for (int b = tid; b < grid_a; b += kWinThreads) {
         const double *w = winpart + ((int64_t)f * grid_a + b) * 3;
         a0 += w[0];
         a1 += w[1];
         a2 += w[2];
     }
-    for (int b = 2 * tid; b < 2 * tid + 2 && b < grid_a; ++b) {
+    for (int b = per * tid; b < per * tid + per && b < grid_a; ++b) {
         uint32_t cb = ccount[(int64_t)f * grid_a + b];
         if (cb > (uint32_t)capb) {
             atomicOr(&ovf, 1u);
@@ -492,7 +498,7 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(SelState *sel, Hi
     const uint32_t off = block_exclusive_scan<uint32_t>(mine, wsu, all_c);
     {
         uint32_t acc = off;
-        for (int b = 2 * tid; b < 2 * tid + 2 && b < grid_a; ++b) {
+        for (int b = per * tid; b < per * tid + per && b < grid_a; ++b) {
             const uint32_t cb = pre[b];
             pre[b] = acc;
             acc += cb;
@@ -707,12 +713,10 @@ hipError_t select_run(const float *z0, const float *z1, int nfields, int64_t n, 
     return hipGetLastError();
 }
 
-hipError_t solver_select(const ZState &zs, SelState *sel, Hist *hist, const double *winpart,
-                         int grid_a, const float *cand, const uint32_t *ccount, int capb,
-                         const uint32_t *stop, uint32_t *fallback_counter, hipStream_t st)
+hipError_t launch_select_window(const void *table, int stride, int ncubes, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_select_window, dim3(2), dim3(kWinThreads), 0, st, sel, hist, winpart,
-                       grid_a, cand, ccount, capb, stop, &zs.sc->hist_slot, fallback_counter);
+    hipLaunchKernelGGL(k_select_window, dim3(2 * ncubes), dim3(kWinThreads), 0, st,
+                       (const char *)table, stride);
     return hipGetLastError();
 }
 

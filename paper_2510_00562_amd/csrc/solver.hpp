@@ -61,45 +61,62 @@ struct DevScalars {
     SelState sel[2];     // 0: s (alpha), 1: t (beta)
     uint32_t fallback;   // full radix searches in the current call
     uint32_t hist_slot;  // 1: sweep A of this launch slot ran a search histogram
-    uint32_t pad;
+    uint32_t call_limit; // iterations this call may do: the cube idles after them
 };
+
+// A cube whose stopping rule holds, or that has done the iterations of the
+// current call, turns every kernel of a launch slot into a no-op.
+__device__ __forceinline__ bool idle(const DevScalars *sc)
+{
+    return sc->stop || sc->calls_iter >= sc->call_limit;
+}
 
 // Offsets (bytes) of every region of a solver workspace.
 struct Layout {
-    size_t scalars, partials, hist, y4p, winpart, cand, ccount;
+    size_t scalars, partials, hist, y4p, winpart, cand, ccount, table;
     size_t u[2], s[2], t[2], w1[2], w2[2];  // FP32 primal, ping-pong
     size_t y1[2], y2[2], y3[2], y4[2];      // duals (FP32 or BF16), ping-pong
     size_t total;
     int dual_bytes;
-    int n_part;    // FP64 partial-sum slots
-    int max_grid;  // upper bound of the sweep A grid
-    int64_t cap;   // candidate capacity per field
+    int n_part;     // FP64 partial-sum slots: 2 per tile, then sweep B blocks
+    int max_tiles;  // sweep A tiles at the smallest band chunk
+    int64_t cap;    // candidate capacity per field
 };
 
-// Tile of the fused primal/dual sweep.
+// Tile of the fused primal/dual sweep: TI x 64 pixels, marching through a
+// chunk of kc bands (kc chosen per cube at run time).
 #ifndef GEO_TILE_ROWS
 #define GEO_TILE_ROWS 16
-#endif
-#ifndef GEO_BAND_CHUNK
-#define GEO_BAND_CHUNK 32
 #endif
 #ifndef GEO_SWEEP_B_ROWS
 #define GEO_SWEEP_B_ROWS 2
 #endif
-constexpr int kTI = GEO_TILE_ROWS, kTJ = 64, kKC = GEO_BAND_CHUNK, kSweepThreads = kTI * kTJ;
+constexpr int kTI = GEO_TILE_ROWS, kTJ = 64, kSweepThreads = kTI * kTJ;
+constexpr int kDefaultKC = 32;       // bands per tile unless the caller picks
+constexpr int kMinKC = 8;
+constexpr int kMaxTiles = 4096;      // tiles of one cube (slices of its search)
+constexpr int kMaxBatch = 64;        // cubes of one batched launch
 constexpr int kPointThreads = 256;
-constexpr int kMaxSweepGrid = 2048;  // persistent grid bound (256 CUs x 8)
-constexpr int kSweepBBlocks = 2048;  // grid-stride blocks of sweep B
+constexpr int kSweepBBlocks = 2048;  // grid-stride blocks of sweep B per cube
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
 struct SweepGrid {
-    int tj, ti, tk;  // tiles along j, i and band chunks
+    int tj, ti, tk, kc;  // tiles along j, i, band chunks; bands per chunk
     __host__ __device__ int blocks() const { return tj * ti * tk; }
 };
-inline SweepGrid sweep_grid(int n1, int n2, int n3)
+inline SweepGrid sweep_grid(int n1, int n2, int n3, int kc)
 {
-    return SweepGrid{ceil_div(n2, kTJ), ceil_div(n1, kTI), ceil_div(n3, kKC)};
+    return SweepGrid{ceil_div(n2, kTJ), ceil_div(n1, kTI), ceil_div(n3, kc), kc};
+}
+// Bands per tile actually used: the request (0 = default), raised until the
+// cube has at most kMaxTiles tiles.
+inline int band_chunk(int n1, int n2, int n3, int requested)
+{
+    int kc = requested > 0 ? requested : kDefaultKC;
+    if (kc < kMinKC) kc = kMinKC;
+    while (sweep_grid(n1, n2, n3, kc).blocks() > kMaxTiles) kc *= 2;
+    return kc;
 }
 inline int point_blocks(int64_t n) { return ceil_div(n, kPointThreads); }
 inline int sweep_b_blocks(int64_t n)
@@ -107,10 +124,9 @@ inline int sweep_b_blocks(int64_t n)
     int b = point_blocks(n);
     return b < kSweepBBlocks ? b : kSweepBBlocks;
 }
-inline int sweep_a_max_grid(int n1, int n2, int n3)
+inline int max_tiles(int n1, int n2, int n3)
 {
-    int t = sweep_grid(n1, n2, n3).blocks();
-    return t < kMaxSweepGrid ? t : kMaxSweepGrid;
+    return sweep_grid(n1, n2, n3, band_chunk(n1, n2, n3, kMinKC)).blocks();
 }
 
 Layout make_layout(int n1, int n2, int n3, int dual_storage);
@@ -129,19 +145,96 @@ struct Side {
     DT *y3, *y4;
 };
 
-struct IterParams {
-    double omega, mu_lo, mu_hi, alpha, beta;
+// Everything the iteration kernels need about one cube. A launch covers a
+// table of these in device memory (one entry for a single cube, up to
+// kMaxBatch for a batch): sweep A walks the concatenated tile list, the
+// search takes one block per (cube, field), sweep B a block range per cube
+// and the finalize one block per cube. Stopped cubes are skipped.
+struct CubeCommon {
+    Dims d;
+    const float *v;
+    DevScalars *sc;
+    double *part;       // [2 * ntiles] tile partials (du2, u2), then sweep B blocks
+    double *winpart;    // [2][ntiles][3] count above, sum above, sum of |z|
+    Hist *hist;         // [2] histograms of the full threshold search
+    float *cand;        // [2][ntiles][capt] candidate slices of the tiles
+    uint32_t *ccount;   // [2][ntiles] candidates appended by each tile
+    int capt;           // candidate capacity of one tile slice
+    int ntiles;
+    SweepGrid g;
+    int tile0;          // first tile of this cube in the launch's tile list
+    int b0, nb;         // sweep B blocks of this cube: first, count
+    float thr1;         // omega * step of w1
+    float mu_lo, mu_hi;
 };
+template <typename DT>
+struct CubeArgs {
+    CubeCommon c;
+    Side<DT> side[2];
+    DT *y4p;            // 5 y4 + u' - v: step 14 before s', t'
+};
+
+// Read-only view of a launch table through the constant address space: its
+// loads are invariant, so the compiler may issue them again where needed
+// instead of keeping every field live in registers (as for kernel
+// arguments). Structs are read field by field.
+template <typename T>
+using const4 = const __attribute__((address_space(4))) T;
+
+template <typename DT>
+__device__ __forceinline__ Side<DT> load_side(const4<Side<DT>> &s)
+{
+    Side<DT> o;
+    o.u = s.u;
+    o.s = s.s;
+    o.t = s.t;
+    o.w1 = s.w1;
+    o.w2 = s.w2;
+    o.y1 = s.y1;
+    o.y2 = s.y2;
+    o.y3 = s.y3;
+    o.y4 = s.y4;
+    return o;
+}
+__device__ __forceinline__ Dims load_dims(const4<Dims> &d)
+{
+    Dims o;
+    o.n1 = d.n1;
+    o.n2 = d.n2;
+    o.n3 = d.n3;
+    o.plane = d.plane;
+    return o;
+}
+
+// Shape of one launch slot over a table of cubes.
+struct LaunchShape {
+    int ncubes;
+    int total_tiles;  // sweep A tiles over all cubes
+    int grid_a;       // persistent sweep A blocks
+    int total_b;      // sweep B blocks over all cubes
+};
+
+// Host image of one cube's table entry (FP32 or BF16 duals: same size).
+struct CubeEntry {
+    unsigned char bytes[sizeof(CubeArgs<float>)];
+};
+static_assert(sizeof(CubeArgs<float>) == sizeof(CubeArgs<bf16>), "one table entry size");
 
 // ---- launchers (kernels in sweep.hip / select.hip / ops.hip) ----
 hipError_t launch_init(const Dims &d, const float *v, void *ws, const Layout &L, double eps,
                        double tol, double alpha, double beta, hipStream_t st);
 hipError_t launch_begin_call(void *ws, const Layout &L, double tol, double alpha, double beta,
-                             hipStream_t st);
-// ev (may be null): 4 events recorded at the phase boundaries (before
-// sweep A, after sweep A, after the threshold search, after sweep B).
-hipError_t launch_iteration(const Dims &d, const float *v, void *ws, const Layout &L,
-                            const IterParams &ip, hipStream_t st, hipEvent_t *ev = nullptr);
+                             int call_limit, hipStream_t st);
+// Fill e for the cube (d, v, ws) with band chunk kc; tile0/b0 place it in
+// the launch; returns its tile and sweep B block counts.
+void cube_entry(CubeEntry *e, const Dims &d, const float *v, void *ws, const Layout &L, double omega,
+                double mu_lo, double mu_hi, int kc, int tile0, int b0, int *ntiles, int *nb);
+int sweep_a_grid(int dual_bytes, int total_tiles);
+// One launch slot over the table (device copy of the entries). ev (may be
+// null): 4 events recorded at the phase boundaries (before sweep A, after
+// sweep A, after the threshold search, after sweep B and the finalize).
+hipError_t launch_slot(const void *table, int dual_bytes, const LaunchShape &sh, hipStream_t st,
+                       hipEvent_t *ev = nullptr);
 // out != null: copy the variable out (FP32); otherwise load it from in.
 hipError_t launch_state_io(const Dims &d, void *ws, const Layout &L, int var, const float *v,
                            float *out, const float *in, hipStream_t st);
@@ -157,21 +250,9 @@ hipError_t select_run(const float *z0, const float *z1, int nfields, int64_t n, 
 hipError_t launch_l1_threshold(const float *x, int64_t n, double radius, SelState *sel,
                                Hist *hist, hipStream_t st);
 hipError_t launch_soft(const float *x, int64_t n, const SelState *sel, float *out, hipStream_t st);
-
-// The solver's per-iteration search: window pass over the candidates, then
-// the full radix search on z evaluated from the state (no-op when the
-// window held tau).
-struct ZState {
-    Dims d;
-    const float *v;
-    const float *s[2], *t[2];   // ping-pong sides
-    const void *y3[2], *y4[2];  // FP32 or BF16 (dual_bytes)
-    int dual_bytes;
-    const DevScalars *sc;       // iteration parity and the lazy y4 factors
-};
-hipError_t solver_select(const ZState &zs, SelState *sel, Hist *hist, const double *winpart,
-                         int grid_a, const float *cand, const uint32_t *ccount, int capb,
-                         const uint32_t *stop, uint32_t *fallback_counter, hipStream_t st);
+// The solver's per-iteration search over a table of cubes (entries of
+// `stride` bytes, CubeCommon first): one block per (cube, field).
+hipError_t launch_select_window(const void *table, int stride, int ncubes, hipStream_t st);
 
 // Standalone projections (ops.hip).
 int l2_blocks(int64_t n);

@@ -26,13 +26,15 @@
 // from the device iteration counter, which makes one iteration's launches a
 // fixed sequence; once the stopping rule holds a device flag turns the
 // remaining launches into no-ops, so iteration counts stay exact.
+#include <string.h>
+
 #include "solver.hpp"
 
 namespace geo {
 
 namespace {
 
-constexpr int TI = kTI, TJ = kTJ, KC = kKC, NT = kSweepThreads;
+constexpr int TI = kTI, TJ = kTJ, NT = kSweepThreads;
 constexpr int H2 = TI + 4, W2 = TJ + 4, S2 = H2 * W2;  // y with a 2-pixel halo
 constexpr int H1 = TI + 2, W1 = TJ + 2, S1 = H1 * W1;  // w' on a 1-pixel ring
 constexpr int HU = TI + 1, WU = TJ + 1, SU = HU * WU;  // u' with the (+1, +1) ring
@@ -44,23 +46,7 @@ static_assert(RING1 <= NT && RINGU <= NT, "at most one ring point per thread");
 constexpr int NPT = 256;  // threads of the pointwise kernels
 
 template <typename DT>
-struct IterArgs {
-    Dims d;
-    const float *v;
-    Side<DT> side[2];
-    DT *y4p;         // 5 y4 + u' - v: step 14 before s', t', in the residual form of y4
-    DevScalars *sc;
-    double *part;    // [grid_a * 2 | blocks_b]
-    double *winpart; // [2][grid_a][3]: count above, sum above, sum of |z|
-    Hist *hist;      // [2] histograms of the full threshold search
-    float *cand;     // [2][grid_a][capb]: per-block slices of candidates
-    uint32_t *ccount;// [2][grid_a]: candidates appended by each block
-    int capb;
-    int grid_a, blocks_b;
-    SweepGrid g;
-    float thr1;      // omega * step_w1
-    float mu_lo, mu_hi;
-};
+using Table = const CubeArgs<DT> *__restrict__;
 
 // Value as stored (FP32 or rounded to BF16), for the l2-ball distance.
 __device__ __forceinline__ float as_stored(const float *, float x) { return x; }
@@ -105,12 +91,13 @@ __device__ __forceinline__ int tile_at(int b, int G, int T, int r)
 }
 
 // One radix level of the full threshold search over z evaluated from the
-// state (bit-identical to the sweeps' own evaluation), for every field whose
-// search is still running; LDS histograms flushed with integer atomics.
+// state (bit-identical to the sweeps' own evaluation) on one tile, for every
+// field of the cube whose search is still running; LDS histograms flushed
+// with integer atomics.
 template <typename DT>
-__device__ void search_histogram(const IterArgs<DT> &a, float *smem)
+__device__ void tile_histogram(const4<CubeArgs<DT>> &a, int i0, int j0, int kb, int ke, float *smem)
 {
-    DevScalars *sc = a.sc;
+    const DevScalars *sc = a.c.sc;
     uint32_t *hc = reinterpret_cast<uint32_t *>(smem);                              // [2][2048]
     unsigned long long *hm = reinterpret_cast<unsigned long long *>(smem + 2 * kHistBins);  // [2][2048]
     for (int b = threadIdx.x; b < 2 * kHistBins; b += NT) {
@@ -126,10 +113,10 @@ __device__ void search_histogram(const IterArgs<DT> &a, float *smem)
         pre[f] = sc->sel[f].prefix;
     }
     __syncthreads();
-    const Dims d = a.d;
+    const Dims d = load_dims(a.c.d);
     const int n1 = d.n1, n2 = d.n2;
     const int par = (int)(sc->iter & 1u);
-    const Side<DT> src = a.side[par];
+    const Side<DT> src = load_side(a.side[par]);
     const float a4 = (float)sc->a4;
     auto add = [&](int f, float z) {
         const uint32_t p = abs_bits(z);
@@ -139,76 +126,68 @@ __device__ void search_histogram(const IterArgs<DT> &a, float *smem)
         atomicAdd(&hc[f * kHistBins + b], 1u);
         atomicAdd(&hm[f * kHistBins + b], (unsigned long long)significand(p));
     };
-    const int64_t stride = (int64_t)gridDim.x * NT;
-    for (int64_t q = (int64_t)blockIdx.x * NT + threadIdx.x; q < d.plane; q += stride) {
-        const float y4 = y4_of(ld(src.y4 + q), a4);
-        if (act[0]) add(0, zs_of(src.s[q], y4));
-        if (act[1]) {
-            const int i = (int)((q / n2) % n1);
-            const float y3c = i <= n1 - 2 ? ld(src.y3 + q) : 0.f;
-            const float y3m = i >= 1 ? ld(src.y3 + q - n2) : 0.f;
-            add(1, zt_of(src.t[q], y3m, y3c, y4));
+    const int i = i0 + (int)threadIdx.x / TJ, j = j0 + (int)threadIdx.x % TJ;
+    if (i < n1 && j < n2)
+        for (int k = kb; k < ke; ++k) {
+            const uint32_t q = ((uint32_t)k * (uint32_t)n1 + (uint32_t)i) * (uint32_t)n2 + (uint32_t)j;
+            const float y4 = y4_of(ld(src.y4 + q), a4);
+            if (act[0]) add(0, zs_of(src.s[q], y4));
+            if (act[1]) {
+                const float y3c = i <= n1 - 2 ? ld(src.y3 + q) : 0.f;
+                const float y3m = i >= 1 ? ld(src.y3 + q - n2) : 0.f;
+                add(1, zt_of(src.t[q], y3m, y3c, y4));
+            }
         }
-    }
     __syncthreads();
     for (int b = threadIdx.x; b < 2 * kHistBins; b += NT) {
         const int f = b / kHistBins, bb = b - f * kHistBins;
         if (hc[b]) {
-            atomicAdd(&a.hist[f].count[bb], hc[b]);
-            atomicAdd((unsigned long long *)&a.hist[f].msum[bb], hm[b]);
+            atomicAdd(&a.c.hist[f].count[bb], hc[b]);
+            atomicAdd((unsigned long long *)&a.c.hist[f].msum[bb], hm[b]);
         }
     }
+    __syncthreads();
+}
+
+// Sums of 8 FP64 values over the block; result valid in thread 0.
+__device__ __forceinline__ void block_sum8(double (&x)[8], double *red /* 8 * NT/64 */)
+{
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = wave_sum(x[q]);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[q * (NT / 64) + wid] = x[q];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            double t = 0.0;
+            for (int w = 0; w < NT / 64; ++w) t += red[q * (NT / 64) + w];
+            x[q] = t;
+        }
 }
 
 template <typename DT>
-__global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
+__global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape sh)
 {
     using P = typename PairOf<DT>::type;
-    DevScalars *sc = a.sc;
-    if (sc->stop) return;
     // [band parity][y1v, y1h, y2v, y2h] masked | u' by band parity |
     // w1', w2' planes read by neighbours (ud_h, lr_v, c_v, c_h)
     __shared__ __align__(16) float smem[2 * 4 * S2 + 2 * SU + 2 * 4 * S1];
     float(*sY)[4][S2] = reinterpret_cast<float(*)[4][S2]>(smem);
     float(*sU)[SU] = reinterpret_cast<float(*)[SU]>(smem + 2 * 4 * S2);
     float(*sW)[4][S1] = reinterpret_cast<float(*)[4][S1]>(smem + 2 * 4 * S2 + 2 * SU);
-    __shared__ double red[NT / 64];
+    __shared__ double red[8 * (NT / 64)];
     __shared__ uint32_t ncand[2];
+    __shared__ int tile0[kMaxBatch + 1];
     static_assert(sizeof(smem) >= 2 * kHistBins * 12, "LDS holds the search histograms");
 
-    // A threshold search that missed its window runs its radix levels in the
-    // launches that follow; the sweep then only histograms z for the field(s)
-    // still searching, and the rest of the launch completes the iteration
-    // once both levels are final.
-    if (!(sc->sel[0].done && sc->sel[1].done)) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) sc->hist_slot = 1u;
-        search_histogram<DT>(a, smem);
-        return;
-    }
-    if (blockIdx.x == 0 && threadIdx.x == 0) sc->hist_slot = 0u;
-
-    const Dims d = a.d;
-    const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
-    const uint32_t N = (uint32_t)d.plane;
-    if (threadIdx.x < 2) ncand[threadIdx.x] = 0u;  // published by the first barrier
-    const int par = (int)(sc->iter & 1u);
-    const Side<DT> src = a.side[par], dst = a.side[par ^ 1];
-    const float a4 = (float)sc->a4;
+    for (int c = threadIdx.x; c <= sh.ncubes; c += NT)
+        tile0[c] = c < sh.ncubes ? cubes[c].c.tile0 : sh.total_tiles;
+    __syncthreads();
     const int tid = threadIdx.x;
     const int oti = tid / TJ, otj = tid % TJ;  // the thread's own point in the tile
-    auto vox32 = [&](int k, int i, int j) {
-        return ((uint32_t)k * (uint32_t)n1 + (uint32_t)i) * (uint32_t)n2 + (uint32_t)j;
-    };
-    float wlo[2], whi[2];
-    bool won[2];
-    for (int f = 0; f < 2; ++f) {
-        won[f] = sc->sel[f].win_on != 0u;
-        wlo[f] = sc->sel[f].win_lo;
-        whi[f] = sc->sel[f].win_hi;
-    }
-    double du2 = 0.0, u2 = 0.0;
-    double s_hi[2] = {0.0, 0.0}, s_all[2] = {0.0, 0.0};
-    float c_hi[2] = {0.f, 0.f};
 
     // ring coordinates (R1-local for w', RU-local for u')
     int rwi = 0, rwj = 0, rui = 0, ruj = 0;
@@ -223,13 +202,53 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
     }
     const bool ring_w = tid < RING1, ring_u = tid < RINGU;
 
-    const int T = a.g.blocks();
     for (int r = 0;; ++r) {
-        const int t = tile_at(blockIdx.x, a.grid_a, T, r);
+        const int t = tile_at(blockIdx.x, sh.grid_a, sh.total_tiles, r);
         if (t < 0) break;
-        const int tj = t % a.g.tj, rest = t / a.g.tj;
-        const int j0 = tj * TJ, i0 = (rest % a.g.ti) * TI, kb = (rest / a.g.ti) * KC;
-        const int ke = min(kb + KC, n3);
+        int cube = 0;
+        while (tile0[cube + 1] <= t) ++cube;
+        // uniform across the block: the cube's entry is read with scalar loads
+        cube = __builtin_amdgcn_readfirstlane(cube);
+        const int lt = __builtin_amdgcn_readfirstlane(t - tile0[cube]);  // tile within the cube
+        const4<CubeArgs<DT>> &a = ((const4<CubeArgs<DT>> *)cubes)[cube];
+        DevScalars *sc = a.c.sc;
+        if (idle(sc)) continue;
+        const SweepGrid g{a.c.g.tj, a.c.g.ti, a.c.g.tk, a.c.g.kc};
+        const int tj = lt % g.tj, rest = lt / g.tj;
+        const int j0 = tj * TJ, i0 = (rest % g.ti) * TI, kb = (rest / g.ti) * g.kc;
+        const Dims d = load_dims(a.c.d);
+        const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
+        const int ke = min(kb + g.kc, n3);
+
+        // A threshold search that missed its window runs its radix levels in
+        // the launch slots that follow; the cube's tiles then only histogram
+        // z for the field(s) still searching, and the rest of the slot
+        // completes the iteration once both levels are final.
+        if (!(sc->sel[0].done && sc->sel[1].done)) {
+            if (tid == 0) sc->hist_slot = 1u;
+            tile_histogram<DT>(a, i0, j0, kb, ke, smem);
+            continue;
+        }
+        if (tid == 0) sc->hist_slot = 0u;
+
+        const uint32_t N = (uint32_t)d.plane;
+        if (tid < 2) ncand[tid] = 0u;  // published by the first barrier of the march
+        const int par = (int)(sc->iter & 1u);
+        const Side<DT> src = load_side(a.side[par]), dst = load_side(a.side[par ^ 1]);
+        const float a4 = (float)sc->a4;
+        auto vox32 = [&](int k, int i, int j) {
+            return ((uint32_t)k * (uint32_t)n1 + (uint32_t)i) * (uint32_t)n2 + (uint32_t)j;
+        };
+        float wlo[2], whi[2];
+        bool won[2];
+        for (int f = 0; f < 2; ++f) {
+            won[f] = sc->sel[f].win_on != 0u;
+            wlo[f] = sc->sel[f].win_lo;
+            whi[f] = sc->sel[f].win_hi;
+        }
+        double du2 = 0.0, u2 = 0.0;
+        double s_hi[2] = {0.0, 0.0}, s_all[2] = {0.0, 0.0};
+        float c_hi[2] = {0.f, 0.f};
         const int oi = i0 + oti, oj = j0 + otj;
         const bool own_in = oi < n1 && oj < n2;
 
@@ -274,7 +293,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
                 const uint32_t q = vox32(kk, oi, oj);
                 ru_u = src.u[q];
                 ru_y4 = ld(src.y4 + q);
-                ru_v = a.v[q];
+                ru_v = a.c.v[q];
                 ru_s = src.s[q];
                 ru_t = src.t[q];
                 ru_y3c = oi <= n1 - 2 ? ld(src.y3 + q) : 0.f;
@@ -318,7 +337,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
             if (kk >= 1) g += dT(buf ^ 1, 2, c);
             y4 = y4_of(y4s, a4);
             const float x = uo - kStepU * (g + y4);
-            return x < a.mu_lo ? a.mu_lo : (x > a.mu_hi ? a.mu_hi : x);
+            return x < a.c.mu_lo ? a.c.mu_lo : (x > a.c.mu_hi ? a.c.mu_hi : x);
         };
         // step 1 (u+), u' and the z inputs of steps 2, 3 for band kk
         auto uphase = [&](int kk, bool own_band) {
@@ -368,8 +387,8 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
                         }
                     }
                 }
-                wave_append(cand, av, a.cand + ((int64_t)f * a.grid_a + blockIdx.x) * a.capb,
-                            &ncand[f], a.capb);
+                wave_append(cand, av, a.c.cand + ((int64_t)f * a.c.ntiles + lt) * a.c.capt,
+                            &ncand[f], a.c.capt);
             }
         };
         // steps 4, 5 and the w extrapolations (9, 10) at one point of band k;
@@ -393,7 +412,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
                     L[3] = mh * yh[c];
                     L[4] = 0.5f * (yv[c] + yv[c - W2]);
                     L[5] = 0.5f * (yh[c] + yh[c - 1]);
-                    const float thr = f ? kStepW : a.thr1;
+                    const float thr = f ? kStepW : a.c.thr1;
                     float wo[6], wn[6];
 #pragma unroll
                     for (int g = 0; g < 3; ++g) {
@@ -498,24 +517,20 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(IterArgs<DT> a)
             if (more) storeY(k & 1);
             __syncthreads();
         }
-    }
 
-    du2 = block_sum<NT>(du2, red);
-    u2 = block_sum<NT>(u2, red);
-    double wsum[2][3];
-    for (int f = 0; f < 2; ++f) {
-        wsum[f][0] = block_sum<NT>((double)c_hi[f], red);
-        wsum[f][1] = block_sum<NT>(s_hi[f], red);
-        wsum[f][2] = block_sum<NT>(s_all[f], red);
-    }
-    if (tid == 0) {
-        a.ccount[blockIdx.x] = ncand[0];
-        a.ccount[a.grid_a + blockIdx.x] = ncand[1];
-        a.part[2 * blockIdx.x] = du2;
-        a.part[2 * blockIdx.x + 1] = u2;
-        for (int f = 0; f < 2; ++f)
-            for (int q = 0; q < 3; ++q)
-                a.winpart[((int64_t)f * a.grid_a + blockIdx.x) * 3 + q] = wsum[f][q];
+        // the tile's FP64 partials: stopping sums, window statistics
+        double acc[8] = {du2, u2, (double)c_hi[0], s_hi[0], s_all[0], (double)c_hi[1], s_hi[1], s_all[1]};
+        block_sum8(acc, red);
+        if (tid == 0) {
+            const int nt = a.c.ntiles;
+            a.c.ccount[lt] = ncand[0];
+            a.c.ccount[nt + lt] = ncand[1];
+            a.c.part[2 * lt] = acc[0];
+            a.c.part[2 * lt + 1] = acc[1];
+            for (int f = 0; f < 2; ++f)
+                for (int q = 0; q < 3; ++q) a.c.winpart[((int64_t)f * nt + lt) * 3 + q] = acc[2 + 3 * f + q];
+        }
+        __syncthreads();  // red and ncand are reused by the next tile
     }
 }
 
@@ -532,12 +547,21 @@ __device__ __forceinline__ float soft(float z, double tau)
 // read twice.
 constexpr int RB = GEO_SWEEP_B_ROWS;
 template <typename DT>
-__global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
+__global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh)
 {
-    DevScalars *sc = a.sc;
-    if (sc->stop || !(sc->sel[0].done && sc->sel[1].done)) return;
     __shared__ double red[NPT / 64];
-    const Dims d = a.d;
+    __shared__ int cube_of_block;
+    if (threadIdx.x == 0) {  // blocks [b0, b0 + nb) belong to one cube
+        int c = 0;
+        while (c + 1 < sh.ncubes && cubes[c + 1].c.b0 <= (int)blockIdx.x) ++c;
+        cube_of_block = c;
+    }
+    __syncthreads();
+    const CubeArgs<DT> &a = cubes[__builtin_amdgcn_readfirstlane(cube_of_block)];
+    DevScalars *sc = a.c.sc;
+    if (idle(sc) || !(sc->sel[0].done && sc->sel[1].done)) return;
+    const int lb = (int)blockIdx.x - a.c.b0;  // block within the cube
+    const Dims d = a.c.d;
     const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
     const int par = (int)(sc->iter & 1u);
     const Side<DT> src = a.side[par], dst = a.side[par ^ 1];
@@ -546,8 +570,8 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
     double r2 = 0.0;
     const uint32_t nstrip = (uint32_t)((n1 + RB - 1) / RB);
     const uint32_t items = (uint32_t)n3 * nstrip * (uint32_t)n2;
-    const uint32_t stride = gridDim.x * NPT;
-    for (uint32_t w = blockIdx.x * NPT + threadIdx.x; w < items; w += stride) {
+    const uint32_t stride = (uint32_t)a.c.nb * NPT;
+    for (uint32_t w = (uint32_t)lb * NPT + threadIdx.x; w < items; w += stride) {
         const uint32_t j = w % (uint32_t)n2, rr = w / (uint32_t)n2;
         const int ia = (int)(rr % nstrip) * RB, k = (int)(rr / nstrip);
         const uint32_t q0 = ((uint32_t)k * (uint32_t)n1 + (uint32_t)ia) * (uint32_t)n2 + j;
@@ -593,7 +617,7 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
         }
     }
     r2 = block_sum<NPT>(r2, red);
-    if (threadIdx.x == 0) a.part[2 * a.grid_a + blockIdx.x] = r2;
+    if (threadIdx.x == 0) a.c.part[2 * a.c.ntiles + lb] = r2;
 }
 
 // Fixed-order sums of the block partials of both sweeps: relative change of u
@@ -601,10 +625,14 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(IterArgs<DT> a)
 // iteration counter. A separate one-block launch: a last-block-done pattern
 // inside sweep B needs a device-scope release per block, which writes back
 // the XCD's L2 each time.
-__global__ __launch_bounds__(NPT) void k_finalize(DevScalars *sc, const double *part, int grid_a,
-                                                 int blocks_b)
+// One block per cube of the table (entries of `stride` bytes).
+__global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
 {
-    if (sc->stop || !(sc->sel[0].done && sc->sel[1].done)) return;
+    const CubeCommon &cc = *reinterpret_cast<const CubeCommon *>(table + (size_t)blockIdx.x * stride);
+    DevScalars *sc = cc.sc;
+    if (idle(sc) || !(sc->sel[0].done && sc->sel[1].done)) return;
+    const double *part = cc.part;
+    const int grid_a = cc.ntiles, blocks_b = cc.nb;
     __shared__ double red[NPT / 64];
     double du2 = 0.0, u2 = 0.0, r2 = 0.0;
     for (int b = threadIdx.x; b < grid_a; b += NPT) {
@@ -665,11 +693,12 @@ __global__ __launch_bounds__(NPT) void k_init(Dims d, const float *v, Side<DT> s
     }
 }
 
-__global__ void k_begin_call(DevScalars *sc, double tol, double alpha, double beta)
+__global__ void k_begin_call(DevScalars *sc, double tol, double alpha, double beta, uint32_t limit)
 {
     if (threadIdx.x == 0) {
         sc->tol = tol;
         sc->calls_iter = 0u;
+        sc->call_limit = limit;
         sc->fallback = 0u;
         sc->sel[0].radius = alpha;
         sc->sel[1].radius = beta;
@@ -797,80 +826,85 @@ int resident_grid()
 }
 
 template <typename DT>
-IterArgs<DT> iter_args(const Dims &d, const float *v, void *ws, const Layout &L, double omega,
-                       double mu_lo, double mu_hi)
+void cube_entry_t(CubeArgs<DT> *a, const Dims &d, const float *v, void *ws, const Layout &L,
+                  double omega, double mu_lo, double mu_hi, int kc, int tile0, int b0, int *ntiles,
+                  int *nb)
 {
     char *b = (char *)ws;
-    IterArgs<DT> a;
-    a.d = d;
-    a.v = v;
-    a.side[0] = side_of<DT>(ws, L, 0);
-    a.side[1] = side_of<DT>(ws, L, 1);
-    a.y4p = (DT *)(b + L.y4p);
-    a.sc = (DevScalars *)(b + L.scalars);
-    a.part = (double *)(b + L.partials);
-    a.winpart = (double *)(b + L.winpart);
-    a.hist = (Hist *)(b + L.hist);
-    a.cand = (float *)(b + L.cand);
-    a.ccount = (uint32_t *)(b + L.ccount);
-    a.g = sweep_grid(d.n1, d.n2, d.n3);
-    const int T = a.g.blocks();
-    int G = resident_grid<DT>();
-    if (G > L.max_grid) G = L.max_grid;
-    if (G >= T) G = T;
-    else if (G >= 8) G &= ~7;
-    a.grid_a = G;
-    a.capb = (int)(L.cap / G);
+    memset(a, 0, sizeof *a);
+    CubeCommon &c = a->c;
+    c.d = d;
+    c.v = v;
+    c.sc = (DevScalars *)(b + L.scalars);
+    c.part = (double *)(b + L.partials);
+    c.winpart = (double *)(b + L.winpart);
+    c.hist = (Hist *)(b + L.hist);
+    c.cand = (float *)(b + L.cand);
+    c.ccount = (uint32_t *)(b + L.ccount);
+    c.g = sweep_grid(d.n1, d.n2, d.n3, band_chunk(d.n1, d.n2, d.n3, kc));
+    c.ntiles = c.g.blocks();
+    c.capt = (int)(L.cap / c.ntiles);
+    c.tile0 = tile0;
     {
         // strips of RB rows; never more blocks than the partials hold
         const int64_t items = (int64_t)d.n3 * ((d.n1 + RB - 1) / RB) * d.n2;
-        const int nb = point_blocks(items);
-        a.blocks_b = nb < kSweepBBlocks ? nb : kSweepBBlocks;
+        const int pb = point_blocks(items);
+        c.nb = pb < kSweepBBlocks ? pb : kSweepBBlocks;
     }
-    a.thr1 = (float)(omega * 0.25);
-    a.mu_lo = (float)mu_lo;
-    a.mu_hi = (float)mu_hi;
-    return a;
+    c.b0 = b0;
+    c.thr1 = (float)(omega * 0.25);
+    c.mu_lo = (float)mu_lo;
+    c.mu_hi = (float)mu_hi;
+    a->side[0] = side_of<DT>(ws, L, 0);
+    a->side[1] = side_of<DT>(ws, L, 1);
+    a->y4p = (DT *)(b + L.y4p);
+    *ntiles = c.ntiles;
+    *nb = c.nb;
 }
 
 template <typename DT>
-hipError_t iteration_t(const Dims &d, const float *v, void *ws, const Layout &L, const IterParams &ip,
-                       hipStream_t st, hipEvent_t *ev)
+hipError_t slot_t(const void *table, const LaunchShape &sh, hipStream_t st, hipEvent_t *ev)
 {
-    IterArgs<DT> a = iter_args<DT>(d, v, ws, L, ip.omega, ip.mu_lo, ip.mu_hi);
-    Hist *hist = (Hist *)((char *)ws + L.hist);
-    ZState zs;
-    zs.d = d;
-    zs.v = v;
-    for (int p = 0; p < 2; ++p) {
-        zs.s[p] = a.side[p].s;
-        zs.t[p] = a.side[p].t;
-        zs.y3[p] = a.side[p].y3;
-        zs.y4[p] = a.side[p].y4;
-    }
-    zs.dual_bytes = L.dual_bytes;
-    zs.sc = a.sc;
+    const CubeArgs<DT> *cubes = (const CubeArgs<DT> *)table;
+    const int stride = (int)sizeof(CubeArgs<DT>);
     if (ev) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_sweep_a<DT>, dim3(a.grid_a), dim3(NT), 0, st, a);
+    hipLaunchKernelGGL(k_sweep_a<DT>, dim3(sh.grid_a), dim3(NT), 0, st, cubes, sh);
     if (ev) (void)hipEventRecord(ev[1], st);
-    hipError_t e = solver_select(zs, a.sc->sel, hist, a.winpart, a.grid_a, a.cand, a.ccount,
-                                 a.capb, &a.sc->stop, &a.sc->fallback, st);
+    hipError_t e = launch_select_window(table, stride, sh.ncubes, st);
     if (e != hipSuccess) return e;
     if (ev) (void)hipEventRecord(ev[2], st);
-    hipLaunchKernelGGL(k_sweep_b<DT>, dim3(a.blocks_b), dim3(NPT), 0, st, a);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(NPT), 0, st, a.sc, (const double *)a.part, a.grid_a,
-                       a.blocks_b);
+    hipLaunchKernelGGL(k_sweep_b<DT>, dim3(sh.total_b), dim3(NPT), 0, st, cubes, sh);
+    hipLaunchKernelGGL(k_finalize, dim3(sh.ncubes), dim3(NPT), 0, st, (const char *)table, stride);
     if (ev) (void)hipEventRecord(ev[3], st);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_iteration(const Dims &d, const float *v, void *ws, const Layout &L,
-                            const IterParams &ip, hipStream_t st, hipEvent_t *ev)
+void cube_entry(CubeEntry *e, const Dims &d, const float *v, void *ws, const Layout &L, double omega,
+                double mu_lo, double mu_hi, int kc, int tile0, int b0, int *ntiles, int *nb)
 {
-    return L.dual_bytes == 2 ? iteration_t<bf16>(d, v, ws, L, ip, st, ev)
-                             : iteration_t<float>(d, v, ws, L, ip, st, ev);
+    if (L.dual_bytes == 2)
+        cube_entry_t<bf16>(reinterpret_cast<CubeArgs<bf16> *>(e->bytes), d, v, ws, L, omega, mu_lo,
+                           mu_hi, kc, tile0, b0, ntiles, nb);
+    else
+        cube_entry_t<float>(reinterpret_cast<CubeArgs<float> *>(e->bytes), d, v, ws, L, omega, mu_lo,
+                            mu_hi, kc, tile0, b0, ntiles, nb);
+}
+
+// Persistent sweep A grid: resident blocks, at most one per tile, a multiple
+// of the 8 XCDs when it is smaller than the tile count.
+int sweep_a_grid(int dual_bytes, int total_tiles)
+{
+    int G = dual_bytes == 2 ? resident_grid<bf16>() : resident_grid<float>();
+    if (G >= total_tiles) return total_tiles;
+    return G >= 8 ? (G & ~7) : G;
+}
+
+hipError_t launch_slot(const void *table, int dual_bytes, const LaunchShape &sh, hipStream_t st,
+                       hipEvent_t *ev)
+{
+    return dual_bytes == 2 ? slot_t<bf16>(table, sh, st, ev) : slot_t<float>(table, sh, st, ev);
 }
 
 hipError_t launch_init(const Dims &d, const float *v, void *ws, const Layout &L, double eps,
@@ -887,10 +921,11 @@ hipError_t launch_init(const Dims &d, const float *v, void *ws, const Layout &L,
 }
 
 hipError_t launch_begin_call(void *ws, const Layout &L, double tol, double alpha, double beta,
-                             hipStream_t st)
+                             int call_limit, hipStream_t st)
 {
     DevScalars *sc = (DevScalars *)((char *)ws + L.scalars);
-    hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(64), 0, st, sc, tol, alpha, beta);
+    hipLaunchKernelGGL(k_begin_call, dim3(1), dim3(64), 0, st, sc, tol, alpha, beta,
+                       (uint32_t)call_limit);
     return hipGetLastError();
 }
 
