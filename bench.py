@@ -19,19 +19,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK = 8.0e12  # MI355X HBM3E bytes/s
-ALGO_BYTES_ITER = 172  # bytes per voxel-iteration, every state word read and written once + v
 
-# Compulsory bytes per voxel of each phase: every array it reads or writes,
-# once (FP32 state and intermediates).
-PHASE_BYTES = {
-    # reads u, w1 (6), w2 (6), y1 (2), y2 (2), y4, v (steps 1, 4, 5, 11, 12 and
-    # the u' part of 14) and s, t, y3 (inputs of the l1 projections of steps 2
-    # and 3); writes u, w1, w2, y1, y2 and y4 + u'/5
-    "sweep_a": 4 * (22 + 18),
-    # reads s, t, y3, y4 and 5 y4 + u' - v; writes s, t, y3, y4 (steps 2, 3,
-    # 13-15; y4 is kept as the residual 5 y4' - v, so v is not needed)
-    "sweep_b": 4 * (5 + 4),
-}
+
+def algo_bytes_iter(db):
+    """Algorithmic bytes per voxel-iteration: the 21 state words read and
+    written once (15 FP32 words of u, s, t, w1, w2; 6 dual words of y1..y4 in
+    db bytes each) plus v: 172 B with FP32 duals, 148 B with BF16."""
+    return 2 * (15 * 4 + 6 * db) + 4
+
+
+def phase_bytes(db):
+    """Compulsory bytes per voxel of each phase (every array it reads or
+    writes, once), duals and the y4 intermediate in db bytes."""
+    return {
+        # reads u, w1 (6), w2 (6), v, s, t (FP32) and y1 (2), y2 (2), y4, y3
+        # (steps 1, 4, 5, 11, 12, the u' part of 14 and the inputs of the l1
+        # projections of steps 2 and 3); writes u, w1, w2 and y1, y2 and
+        # 5 y4 + u' - v
+        "sweep_a": 4 * 16 + db * 6 + 4 * 13 + db * 5,
+        # reads s, t and y3, y4, 5 y4 + u' - v; writes s, t and y3, y4 (steps
+        # 2, 3, 13-15; y4 is kept as the residual 5 y4' - v, so v is not read)
+        "sweep_b": 4 * 2 + db * 3 + 4 * 2 + db * 2,
+    }
+
+
+PHASE_BYTES = phase_bytes(4)
+ALGO_BYTES_ITER = algo_bytes_iter(4)
 
 
 def parse():
@@ -40,6 +53,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--cube", default="256x256x128", help="N1xN2xN3")
+    ap.add_argument("--workload", choices=("cube", "batch"), default="cube",
+                    help="cube: one cube (default); batch: 32 uneven cubes, batched launches "
+                         "vs the per-cube loop")
+    ap.add_argument("--dual", choices=("f32", "bf16"), default="f32",
+                    help="storage of the dual variables y1..y4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
@@ -116,20 +134,25 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               "design is described but not built.", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch":
+        return bench_batch(args)
     import numpy as np
     import torch
 
     import paper_2510_00562_amd as geo
-    from synth.cubes import CUBE_256x256x128, like, make_cube
+    from synth.cubes import CUBE_256x256x128, CUBE_512x512x224, like, make_cube
 
     n1, n2, n3 = (int(x) for x in args.cube.lower().split("x"))
-    spec = CUBE_256x256x128 if (n1, n2, n3) == (256, 256, 128) else like(CUBE_256x256x128, n1=n1,
-                                                                          n2=n2, n3=n3)
+    named = {(256, 256, 128): CUBE_256x256x128, (512, 512, 224): CUBE_512x512x224}
+    spec = named.get((n1, n2, n3)) or like(CUBE_256x256x128, n1=n1, n2=n2, n3=n3)
     c = make_cube(spec)
     v = torch.from_numpy(np.ascontiguousarray(c["v"], dtype=np.float32)).cuda()
     N = v.numel()
     dims = geo.dims_of(v.shape)
-    p = geo.params(c["eps"], c["alpha"], c["beta"], omega=c["omega"], tol=0.0)
+    db = 2 if args.dual == "bf16" else 4
+    PB = phase_bytes(db)
+    p = geo.params(c["eps"], c["alpha"], c["beta"], omega=c["omega"], tol=0.0,
+                   dual_storage=geo.GEO_STORE_BF16 if db == 2 else geo.GEO_STORE_F32)
     ws = geo.Workspace(geo.geo_workspace_size(dims, p))
     geo.geo_state_init(dims, p, v, ws)
     geo.geo_step(dims, p, v, ws, args.warmup)
@@ -140,10 +163,11 @@ def main():
     el = time.perf_counter() - t0
     K = args.steps
     value = N * K / el
-    dom = max(PHASE_BYTES, key=lambda k: phase_ms[k])
+    dom = max(PB, key=lambda k: phase_ms[k])
     avg_s = phase_ms[dom] / K / 1e3
-    achieved = PHASE_BYTES[dom] * N / avg_s
-    traffic = read_traffic(args.traffic, f"{n1}x{n2}x{n3}") if dom == "sweep_a" else None
+    achieved = PB[dom] * N / avg_s
+    traffic = (read_traffic(args.traffic, f"{n1}x{n2}x{n3}")
+               if dom == "sweep_a" and db == 4 else None)
     out = {
         "metric": "P-PDS voxel-iterations/s",
         "value": value,
@@ -158,20 +182,103 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"P-PDS (Alg. 1) on one {n1}x{n2}x{n3} cube, synthetic mixed "
-                               "noise, FP32 iterates, FP64 reductions",
-                   "n1": n1, "n2": n2, "n3": n3, "voxels": N, "omega": c["omega"]},
+                               "noise, FP32 iterates" + (", BF16-stored duals" if db == 2 else "")
+                               + ", FP64 reductions",
+                   "n1": n1, "n2": n2, "n3": n3, "voxels": N, "omega": c["omega"],
+                   "dual_storage": args.dual},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved / 1e9,
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
-                     "traffic": traffic, "bytes_per_voxel": PHASE_BYTES[dom],
+                     "traffic": traffic, "bytes_per_voxel": PB[dom],
                      "traffic_bytes_per_voxel": None if traffic is None else traffic / N,
                      "avg_launch_ms": 1e3 * avg_s},
-        "iteration_hbm_frac": ALGO_BYTES_ITER * value / HBM_PEAK,
+        "iteration_hbm_frac": algo_bytes_iter(db) * value / HBM_PEAK,
         "phase_ms_per_step": {k: v_ / K for k, v_ in phase_ms.items()},
         "last": {"rel_change": res.rel_change, "r": res.r, "tau_s": res.tau_s,
                  "tau_t": res.tau_t, "iters": res.total_iters},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def bench_batch(args):
+    """32 uneven cubes: the batched launches (persistent sweep over every
+    cube's tiles, one graph-replayed launch sequence per iteration, band
+    chunk from the autotuner) against the per-cube loop (geo_step on each
+    cube in turn) on the same GPU, same iterations, same results (the
+    batched iterates are bit-identical to the per-cube ones)."""
+    import numpy as np
+    import torch
+
+    import paper_2510_00562_amd as geo
+    from paper_2510_00562_amd.tune import tune_band_chunk
+    from synth.cubes import batch_specs, make_cube
+
+    specs = batch_specs()
+    db = 2 if args.dual == "bf16" else 4
+    store = geo.GEO_STORE_BF16 if db == 2 else geo.GEO_STORE_F32
+    dims, ps, vs, wss = [], [], [], []
+    for spec in specs:
+        c = make_cube(spec)
+        v = torch.from_numpy(np.ascontiguousarray(c["v"], dtype=np.float32)).cuda()
+        d = geo.dims_of(v.shape)
+        p = geo.params(c["eps"], c["alpha"], c["beta"], omega=c["omega"], dual_storage=store)
+        dims.append(d)
+        ps.append(p)
+        vs.append(v)
+        wss.append(geo.Workspace(geo.geo_workspace_size(d, p)))
+    total = sum(v.numel() for v in vs)
+    table = geo.Workspace(geo.geo_batch_table_size(len(vs)))
+    kc, tune_ms = tune_band_chunk(dims, ps, vs, wss, table)
+    K, W = args.steps, args.warmup
+
+    # per-cube loop: each cube alone, one after the other
+    for d, p, v, ws in zip(dims, ps, vs, wss):
+        geo.geo_state_init(d, p, v, ws)
+        geo.geo_step(d, p, v, ws, W)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for d, p, v, ws in zip(dims, ps, vs, wss):
+        geo.geo_step(d, p, v, ws, K)
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter() - t0
+
+    # batched: every cube in one launch sequence per iteration
+    for d, p, v, ws in zip(dims, ps, vs, wss):
+        geo.geo_state_init(d, p, v, ws)
+    geo.geo_batch_step(dims, ps, vs, wss, table, W, use_graph=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, res = geo.geo_batch_step(dims, ps, vs, wss, table, K, use_graph=True)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    assert all(r.iters == K for r in res)
+    value = total * K / t_batch
+    out = {
+        "metric": "P-PDS voxel-iterations/s",
+        "value": value,
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": W,
+        "ms_per_step": 1e3 * t_batch / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"P-PDS (Alg. 1) on a batch of {len(vs)} uneven cubes "
+                               "(N1, N2 in 64..256, N3 in 32..190), batched launches with "
+                               "HIP graph replay", "cubes": len(vs), "voxels": total,
+                   "dual_storage": args.dual, "band_chunk": kc},
+        "roofline": {"bound": "hbm", "kernel": "whole iteration",
+                     "achieved": algo_bytes_iter(db) * value / 1e9, "peak": HBM_PEAK / 1e9,
+                     "unit": "GB/s", "frac": algo_bytes_iter(db) * value / HBM_PEAK,
+                     "traffic": None, "bytes_per_voxel": algo_bytes_iter(db)},
+        "per_cube_loop": {"value": total * K / t_loop, "ms_per_step": 1e3 * t_loop / K},
+        "speedup_vs_per_cube_loop": t_loop / t_batch,
+        "tuner_ms_per_iteration": tune_ms,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -158,3 +158,34 @@ def random_state(shape, seed, scale=0.1):
 
 def random_cube(shape, seed, lo=-1.0, hi=1.0):
     return np.random.default_rng(seed).uniform(lo, hi, size=shape)
+
+
+def batch_specs(n: int = 32, seed: int = 2):
+    """The uneven batch: n cubes with N1, N2 ~ U{64..256}, N3 ~ U{32..190},
+    Gaussian sigma ~ U[0.02, 0.15], the other noise parts as for the
+    256 x 256 x 128 cube; dimensions and sigmas from rng(seed), cube c
+    generated from seed 2000 + c."""
+    rng = np.random.default_rng(seed)
+    n1 = rng.integers(64, 257, size=n)
+    n2 = rng.integers(64, 257, size=n)
+    n3 = rng.integers(32, 191, size=n)
+    sig = rng.uniform(0.02, 0.15, size=n)
+    return [like(CUBE_256x256x128, n1=int(n1[c]), n2=int(n2[c]), n3=int(n3[c]),
+                 sigma=float(sig[c]), seed=2000 + c) for c in range(n)]
+
+
+def serving_specs(n: int, rate: float, seed: int = 4):
+    """A request stream: Poisson arrivals at `rate` per second, sizes drawn
+    from {128x128x64, 256x256x128, 256x256x190, 512x512x224} with weights
+    {0.4, 0.3, 0.2, 0.1}, noise as for the 256 x 256 x 128 cube; arrivals and
+    sizes from rng(seed), request q generated from seed 40000 + q. Returns
+    [(arrival seconds, CubeSpec)]."""
+    rng = np.random.default_rng(seed)
+    sizes = [(128, 128, 64), (256, 256, 128), (256, 256, 190), (512, 512, 224)]
+    pick = rng.choice(len(sizes), size=n, p=[0.4, 0.3, 0.2, 0.1])
+    t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+    out = []
+    for q in range(n):
+        a, b, k = sizes[pick[q]]
+        out.append((float(t[q]), like(CUBE_256x256x128, n1=a, n2=b, n3=k, seed=40000 + q)))
+    return out
