@@ -189,3 +189,77 @@ def serving_specs(n: int, rate: float, seed: int = 4):
         a, b, k = sizes[pick[q]]
         out.append((float(t[q]), like(CUBE_256x256x128, n1=a, n2=b, n3=k, seed=40000 + q)))
     return out
+
+
+# ---- the paper's five noise cases (Sec. IV-A) on a synthetic clean cube ----
+CASES = {
+    1: dict(gauss=True, sparse=False, stripe=False, dead=False),
+    2: dict(gauss=True, sparse=True, stripe=False, dead=False),
+    3: dict(gauss=True, sparse=False, stripe=True, dead=False),
+    4: dict(gauss=True, sparse=False, stripe=False, dead=True),
+    5: dict(gauss=True, sparse=True, stripe=True, dead=True),
+}
+CASE_SIGMA, CASE_PS, CASE_PT, CASE_PD = 0.1, 0.05, 0.05, 0.01
+CASE_WIDTHS = (1, 2, 3)
+
+
+def paper_case(case: int, n1: int, n2: int, n3: int, seed: int = 0, omega: float = 0.03,
+               endmembers: int = 6, cells: int = 24) -> dict:
+    """A cube with noise case 1..5 of Sec. IV-A and the radii of eqs.
+    (25)-(27):
+      Gaussian sigma 0.1 (every case); salt and pepper at rate 0.05 (cases
+      2, 5); vertical stripes, each column of each band with probability
+      0.05 offset by U[-0.5, 0.5] (cases 3, 5); deadlines (cases 4, 5): in
+      every band each column starts with probability 0.01 a run of zero
+      columns of width U{1, 2, 3}.
+      alpha = rho N (0.5 p_s + mean(v) c_d), beta = rho 0.5 N p_t (1 - p_s)
+      (1 - c_d) / 2, eps = rho sqrt(sigma^2 N (1 - p_s)(1 - c_d)), with the
+      deadline coverage c_d = 1 - exp(-mean width * p_d) and rho = 0.98,
+      0.95, 0.90 for one, two, three nonzero radii (cases 1, 2-4, 5).
+    The clean cube follows G1-G3. Returns the dict of make_cube."""
+    flags = CASES[case]
+    rng = np.random.default_rng(seed)
+    f = _endmembers(rng, endmembers, n3)
+    a = _abundances(rng, n1, n2, endmembers, cells)
+    u = np.einsum("ije,ek->kij", a, f)
+    n = rng.normal(0.0, CASE_SIGMA, size=u.shape)
+    t = np.zeros_like(u)
+    p_s = CASE_PS if flags["sparse"] else 0.0
+    p_t = CASE_PT if flags["stripe"] else 0.0
+    p_d = CASE_PD if flags["dead"] else 0.0
+    if p_t:
+        hit_col = rng.uniform(size=(n3, n2)) < p_t
+        off = rng.uniform(-0.5, 0.5, size=(n3, n2))
+        t += (hit_col * off)[:, None, :]
+    v = u + t + n
+    hit = np.zeros(u.shape, dtype=bool)
+    if p_s:
+        sp = rng.uniform(size=u.shape) < p_s
+        val = (rng.uniform(size=u.shape) < 0.5).astype(np.float64)
+        v[sp] = val[sp]
+        hit |= sp
+    if p_d:
+        start = rng.uniform(size=(n3, n2)) < p_d
+        width = rng.choice(CASE_WIDTHS, size=(n3, n2))
+        dead = np.zeros((n3, n2), dtype=bool)
+        for k, j in zip(*np.nonzero(start)):
+            dead[k, j:j + width[k, j]] = True
+        v = np.where(dead[:, None, :], 0.0, v)
+        hit |= np.broadcast_to(dead[:, None, :], u.shape)
+    n = np.where(hit, 0.0, n)
+    s = np.where(hit, v - u - t, 0.0)
+    N = u.size
+    c_d = 1.0 - np.exp(-np.mean(CASE_WIDTHS) * p_d)
+    nonzero = 1 + (p_s > 0 or p_d > 0) + (p_t > 0)
+    rho = {1: 0.98, 2: 0.95, 3: 0.90}[nonzero]
+    alpha = rho * N * (0.5 * p_s + float(v.mean()) * c_d)
+    beta = rho * 0.5 * N * p_t * (1 - p_s) * (1 - c_d) / 2
+    eps = rho * np.sqrt(CASE_SIGMA ** 2 * N * (1 - p_s) * (1 - c_d))
+    return dict(u_clean=u, v=v, n=n, s_bar=s, t_bar=t, eps=float(eps), alpha=float(alpha),
+                beta=float(beta), mu_lo=0.0, mu_hi=1.0, omega=omega, shape=(n3, n1, n2),
+                case=case, rho=rho, c_d=c_d)
+
+
+# Shapes of the paper's two simulated-noise images (Sec. IV-A).
+PAVIA_SHAPE = (120, 120, 99)    # N1, N2, N3
+JASPER_SHAPE = (100, 100, 198)
