@@ -67,8 +67,11 @@ typedef struct {
     double omega;        /* GeoSSTV balance of eq. (13), >= 0               */
     int32_t max_iter;    /* iteration cap, >= 1 (geo_solve)                 */
     double tol;          /* stop after the first iteration with
-                            ||u+ - u||_2 / ||u||_2 < tol (eq. (28));
-                            tol <= 0 runs exactly max_iter iterations      */
+                            ||u+ - u||_2 / ||u||_2 < tol (eq. (28)), not
+                            counting the first iteration after
+                            geo_state_init (from zero duals it changes u
+                            only by the box projection); tol <= 0 runs
+                            exactly max_iter iterations                    */
     int32_t dual_storage;/* GEO_STORE_F32 or GEO_STORE_BF16                 */
     int32_t check_every; /* iterations between host checks of the stopping
                             flag (0 = 32); the count returned is exact

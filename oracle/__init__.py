@@ -74,7 +74,7 @@ def _setup(L):
     st = [_dp] * 9
     L.ora_init.argtypes = [i, i, i, _dp] + st
     L.ora_step.argtypes = [i, i, i, ctypes.POINTER(Params), _dp] + st + [_dp]
-    L.ora_run.argtypes = [i, i, i, ctypes.POINTER(Params), _dp] + st + [i, d, _dp]
+    L.ora_run.argtypes = [i, i, i, ctypes.POINTER(Params), _dp] + st + [i, d, i, _dp]
     L.ora_run.restype = i
     L.ora_step_sizes.argtypes = [_dp]
     L.ora_set_threads.argtypes = [i]
@@ -234,7 +234,7 @@ class Solver:
         lib().ora_set_threads(threads_for(self.v.size))
         tr = np.zeros(4 * max(n, 1))
         done = lib().ora_run(*self.dims, ctypes.byref(self.params), _p(self.v), *self._ptrs(),
-                             n, tol, _p(tr))
+                             n, tol, len(self.trace), _p(tr))
         self.trace.extend(tuple(tr[4 * q:4 * q + 4]) for q in range(done))
         return done
 

@@ -550,12 +550,16 @@ void ora_step(int n1, int n2, int n3, const ora_params *p, const double *v,
 }
 
 /* Run the loop of Alg. 1: at most max_iter passes, stopping after the first
- * pass whose stopping quantity is below tol (tol <= 0: run all passes).
+ * pass whose stopping quantity (eq. (28)) is below tol (tol <= 0: run all
+ * passes). done_before: passes made since the initial point by earlier
+ * calls. The rule is not applied to the first pass after the initial point:
+ * from u = v with zero duals that pass changes u only by the box projection,
+ * so a cube already inside the box would stop there unchanged.
  * trace_all (may be NULL) gets 4 numbers per pass. Returns the pass count. */
 int ora_run(int n1, int n2, int n3, const ora_params *p, const double *v,
             double *u, double *s, double *t, double *w1, double *w2,
             double *y1, double *y2, double *y3, double *y4,
-            int max_iter, double tol, double *trace_all)
+            int max_iter, double tol, int done_before, double *trace_all)
 {
     double tr[4];
     int it = 0;
@@ -564,7 +568,7 @@ int ora_run(int n1, int n2, int n3, const ora_params *p, const double *v,
         step_ws(n1, n2, n3, p, v, u, s, t, w1, w2, y1, y2, y3, y4, tr, ws);
         if (trace_all) memcpy(trace_all + 4 * it, tr, sizeof tr);
         ++it;
-        if (tol > 0.0 && tr[0] < tol) break;
+        if (tol > 0.0 && done_before + it >= 2 && tr[0] < tol) break;
     }
     free(ws);
     return it;

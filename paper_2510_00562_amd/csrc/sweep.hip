@@ -654,7 +654,9 @@ __global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
         sc->iter = sc->iter + 1u;
         sc->calls_iter = sc->calls_iter + 1u;
         if (bad) sc->nonfinite = 1u;
-        if (bad || (sc->tol > 0.0 && rel < sc->tol)) sc->stop = 1u;
+        // eq. (28), from the second iteration after the initial point on: the
+        // first one (zero duals) changes u only by the box projection
+        if (bad || (sc->tol > 0.0 && sc->iter >= 2u && rel < sc->tol)) sc->stop = 1u;
     }
 }
 

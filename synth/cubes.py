@@ -263,3 +263,27 @@ def paper_case(case: int, n1: int, n2: int, n3: int, seed: int = 0, omega: float
 # Shapes of the paper's two simulated-noise images (Sec. IV-A).
 PAVIA_SHAPE = (120, 120, 99)    # N1, N2, N3
 JASPER_SHAPE = (100, 100, 198)
+
+
+# ---- the paper's real-image experiment (Sec. IV-B), synthetic stand-ins ----
+# (N1, N2, N3), fixed radii (alpha, beta, eps), omega
+REAL_SHAPES = {
+    "indian_pines_shape": ((120, 120, 198), (200.0, 100.0, 30.0), 0.01),
+    "suwannee_shape": ((100, 100, 360), (800.0, 5000.0, 100.0), 0.01),
+}
+
+
+def real_shape_case(name: str, seed: int = 9) -> dict:
+    """A synthetic cube of the shape of one of the paper's real images, with
+    its fixed radii (the data itself is not available). The noise levels are
+    chosen so that those radii are 0.98 of the noise norms: Gaussian sigma =
+    eps / (0.98 sqrt(N)), salt and pepper at rate 2 alpha / (0.98 N), stripes
+    on a fraction beta / (0.98 * 0.25 N) of the columns."""
+    (n1, n2, n3), (alpha, beta, eps), omega = REAL_SHAPES[name]
+    N = n1 * n2 * n3
+    spec = like(CUBE_256x256x128, n1=n1, n2=n2, n3=n3, sigma=eps / (0.98 * np.sqrt(N)),
+                p_s=2 * alpha / (0.98 * N), p_t=beta / (0.98 * 0.25 * N), p_d=0.0, c_d=0.0,
+                seed=seed, omega=omega)
+    c = make_cube(spec)
+    c.update(eps=eps, alpha=alpha, beta=beta, omega=omega)
+    return c

@@ -146,3 +146,18 @@ def test_constant_cube_fixed_point_on_gpu():
     np.testing.assert_allclose(g["u"], f32(v), atol=1e-7)
     for n in ("s", "t", "w1", "w2", "y1", "y2", "y3"):
         assert np.abs(g[n]).max() < 1e-6, n
+
+
+def test_stopping_rule_starts_at_the_second_iteration(ora):
+    """A cube inside the box: the first iteration leaves u = v exactly, and
+    both sides apply eq. (28) from the second iteration on."""
+    announce("stopping rule, first iteration exempt")
+    c = make_cube(like(SMALL_64x64x16, n1=30, n2=41, n3=6, seed=12, sigma=0.01, p_s=0.0, p_t=0.02))
+    v = np.clip(f32(c["v"]), 0.05, 0.95)
+    prm = dict(eps=c["eps"], alpha=c["alpha"] + 1.0, beta=c["beta"], omega=0.03, tol=1e-3)
+    geo, dims, p, ws, vd = gpu_solver(v.shape, v, prm)
+    res = geo.geo_step(dims, p, vd, ws, 300)
+    S = ora.Solver(v, prm["eps"], prm["alpha"], prm["beta"], omega=0.03)
+    done = S.step(300, tol=1e-3)
+    assert S.trace[0][0] == 0.0
+    assert res.iters > 1 and abs(done - res.iters) <= 1

@@ -208,3 +208,19 @@ def test_limit_satisfies_optimality_conditions(ora, seed):
     mu = (y4 @ r) / (r @ r)
     assert mu > 0
     np.testing.assert_allclose(y4, mu * r, atol=tol)
+
+
+def test_stopping_rule_skips_the_first_iteration(ora):
+    """Reading of eq. (28) with the initial point u = v and zero duals: the
+    first iteration only projects u onto the box, so for a cube inside the box
+    ||u1 - u0|| = 0; the rule starts with the second iteration (the loop
+    would otherwise return v unchanged)."""
+    rng = np.random.default_rng(5)
+    v = rng.uniform(0.2, 0.8, size=(3, 6, 7))
+    S = ora.Solver(v, 0.5, 1.0, 1.0, omega=0.03)
+    assert S.step(50, tol=0.5) == 2
+    assert S.trace[0][0] == 0.0 and S.trace[1][0] > 0.0
+    # split calls count iterations since the initial point
+    S2 = ora.Solver(v, 0.5, 1.0, 1.0, omega=0.03)
+    assert S2.step(1, tol=0.5) == 1
+    assert S2.step(50, tol=0.5) == 1
