@@ -307,6 +307,72 @@ __device__ __forceinline__ T block_exclusive_scan(T x, T *wsum, T &total)
     return before + inc - x;
 }
 
+// Two block-wide exclusive prefix sums at once (the shuffles of the two
+// chains interleave). wsum: 2 * kWinThreads/64 entries of LDS.
+__device__ __forceinline__ void block_exclusive_scan2(double &a, double &b, double *wsum,
+                                                      double &ta, double &tb)
+{
+    constexpr int NW = kWinThreads / 64;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double ia = a, ib = b;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const double ya = __shfl_up(ia, o, 64), yb = __shfl_up(ib, o, 64);
+        if (lane >= o) {
+            ia += ya;
+            ib += yb;
+        }
+    }
+    if (lane == 63) {
+        wsum[w] = ia;
+        wsum[NW + w] = ib;
+    }
+    __syncthreads();
+    double ba = 0.0, bb = 0.0, sa = 0.0, sb = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        const double va = wsum[q], vb = wsum[NW + q];
+        if (q < w) {
+            ba += va;
+            bb += vb;
+        }
+        sa += va;
+        sb += vb;
+    }
+    __syncthreads();
+    ta = sa;
+    tb = sb;
+    a = ba + ia - a;
+    b = bb + ib - b;
+}
+
+// Block-wide sums of three values (fixed order); every thread gets them.
+__device__ __forceinline__ void block_sum3(double &a, double &b, double &c, double *wsum)
+{
+    constexpr int NW = kWinThreads / 64;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        a += __shfl_xor(a, o, 64);
+        b += __shfl_xor(b, o, 64);
+        c += __shfl_xor(c, o, 64);
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+        wsum[w] = a;
+        wsum[NW + w] = b;
+        wsum[2 * NW + w] = c;
+    }
+    __syncthreads();
+    a = b = c = 0.0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+        a += wsum[q];
+        b += wsum[NW + q];
+        c += wsum[2 * NW + q];
+    }
+    __syncthreads();
+}
+
 __device__ __forceinline__ double bin_value(unsigned long long msum, uint32_t first_pattern)
 {
     const uint32_t e = first_pattern >> 23;
@@ -320,7 +386,7 @@ __device__ __forceinline__ double bin_value(unsigned long long msum, uint32_t fi
 __device__ void level_step(SelState *sel, Hist *hist, int f)
 {
     __shared__ SelState s;
-    __shared__ double wsd[kWinThreads / 64];
+    __shared__ double wsd[3 * (kWinThreads / 64)];
     __shared__ int best;
     __shared__ int fin;
     const int tid = threadIdx.x;
@@ -343,8 +409,10 @@ __device__ void level_step(SelState *sel, Hist *hist, int f)
         tc += (double)hist[f].count[b];
     }
     double allS, allC;
-    double S = s.s_above + block_exclusive_scan<double>(ts, wsd, allS);
-    double C = (double)s.c_above + block_exclusive_scan<double>(tc, wsd, allC);
+    double xS = ts, xC = tc;
+    block_exclusive_scan2(xS, xC, wsd, allS, allC);
+    double S = s.s_above + xS;
+    double C = (double)s.c_above + xC;
     const double radius = s.radius;
     int mine = -1;
     double mS = 0.0, mC = 0.0, mbs = 0.0, mbc = 0.0, mfb = 0.0;
@@ -447,7 +515,7 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
     __shared__ unsigned long long ms[kWinBins];
     __shared__ uint32_t pre[kMaxTiles];
     __shared__ float cl[kCandLds + 64];  // staged candidates (+ one wave of slack)
-    __shared__ double wsd[kWinThreads / 64];
+    __shared__ double wsd[3 * (kWinThreads / 64)];
     __shared__ uint32_t wsu[kWinThreads / 64];
     __shared__ double tot[3];
     __shared__ int verdict;  // 0 searching, 1 done, 2 full search needed
@@ -504,10 +572,8 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
             acc += cb;
         }
     }
-    double t0, t1, t2;
-    (void)block_exclusive_scan<double>(a0, wsd, t0);
-    (void)block_exclusive_scan<double>(a1, wsd, t1);
-    (void)block_exclusive_scan<double>(a2, wsd, t2);
+    block_sum3(a0, a1, a2, wsd);
+    const double t0 = a0, t1 = a1, t2 = a2;
     if (tid == 0) {
         ctot = all_c;
         tot[0] = t0;
@@ -562,11 +628,29 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         // the candidates sit in per-block slices written by sweep A; a flat
         // index maps to a slice by binary search over the prefix sums, so
         // every thread issues independent loads
-        for (int q = tid; q < total; q += kWinThreads) {
+        if (staged) {
+            // four candidates per step, so their LDS reads overlap
+            for (int q0 = tid; q0 < total; q0 += 4 * kWinThreads) {
+                uint32_t pq[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int q = q0 + u * kWinThreads;
+                    pq[u] = q < total ? __float_as_uint(cl[q]) : 0u;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const uint32_t p = pq[u];
+                    if (q0 + u * kWinThreads < total && p >= base && p < lim) {
+                        const uint32_t b = (p - base) >> shift;
+                        atomicAdd(&cnt[b], 1u);
+                        atomicAdd(&ms[b], (unsigned long long)significand(p));
+                    }
+                }
+            }
+        }
+        for (int q = staged ? total : tid; q < total; q += kWinThreads) {
             uint32_t p;
-            if (staged) {
-                p = __float_as_uint(cl[q]);
-            } else {
+            {
                 int lo = 0, hi = grid_a - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
@@ -588,9 +672,10 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         const bool valid = b < nb;
         const double bs = valid ? bin_value(ms[b], base + ((uint32_t)b << shift)) : 0.0;
         const double bc = valid ? (double)cnt[b] : 0.0;
-        double allS, allC;
-        const double aboveS = Sab + block_exclusive_scan<double>(bs, wsd, allS);
-        const double aboveC = Cab + block_exclusive_scan<double>(bc, wsd, allC);
+        double allS, allC, xS = bs, xC = bc;
+        block_exclusive_scan2(xS, xC, wsd, allS, allC);
+        const double aboveS = Sab + xS;
+        const double aboveC = Cab + xC;
         const double radius = s.radius;
         const double S = aboveS + bs, C = aboveC + bc;  // values >= bin b's first edge
         const float eb = valid ? __uint_as_float(base + ((uint32_t)b << shift)) : 0.f;

@@ -97,7 +97,10 @@ constexpr int kMinKC = 8;
 constexpr int kMaxTiles = 4096;      // tiles of one cube (slices of its search)
 constexpr int kMaxBatch = 64;        // cubes of one batched launch
 constexpr int kPointThreads = 256;
-constexpr int kSweepBBlocks = 2048;  // grid-stride blocks of sweep B per cube
+#ifndef GEO_SWEEP_B_BLOCKS
+#define GEO_SWEEP_B_BLOCKS 2048
+#endif
+constexpr int kSweepBBlocks = GEO_SWEEP_B_BLOCKS;  // grid-stride blocks of sweep B per cube
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
