@@ -130,6 +130,14 @@ int geo_step_profiled(geo_dims dims, const geo_params *p, const float *v,
                       void *ws, size_t ws_bytes, int32_t n_iter, void *stream,
                       geo_result *out, double *phase_ms);
 
+/* geo_step with two HIP events per iteration around the fused sweep only
+ * (its launch time for a roofline, at a fraction of geo_step_profiled's
+ * event cost). *sweep_a_ms (host) receives the summed GPU time of that
+ * kernel over the call. */
+int geo_step_timed(geo_dims dims, const geo_params *p, const float *v,
+                   void *ws, size_t ws_bytes, int32_t n_iter, void *stream,
+                   geo_result *out, double *sweep_a_ms);
+
 /* geo_state_init + geo_step(max_iter) + copy of u, s, t (N floats each). */
 int geo_solve(geo_dims dims, const geo_params *p, const float *v,
               float *u, float *s, float *t, void *ws, size_t ws_bytes,

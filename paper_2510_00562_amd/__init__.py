@@ -88,6 +88,8 @@ def lib():
             "geo_solve": [geo_dims, P, _vp, _vp, _vp, _vp, _vp, _sz, _vp, R],
             "geo_step_profiled": [geo_dims, P, _vp, _vp, _sz, i32, _vp, R,
                                   ctypes.POINTER(ctypes.c_double)],
+            "geo_step_timed": [geo_dims, P, _vp, _vp, _sz, i32, _vp, R,
+                               ctypes.POINTER(ctypes.c_double)],
             "geo_state_get": [geo_dims, P, _vp, _sz, i32, _vp, _vp, _vp],
             "geo_state_set": [geo_dims, P, _vp, _sz, i32, _vp, _vp, _vp],
             "geo_apply_op": [i32, i32, geo_dims, _vp, _vp, _vp],
@@ -209,6 +211,17 @@ def geo_step_profiled(dims, p, v, ws: Workspace, n_iter: int, stream=None):
                                    _stream(stream), ctypes.byref(out), ms),
            "geo_step_profiled", allow_maxiter=True)
     return out, dict(zip(PHASES, list(ms)))
+
+
+def geo_step_timed(dims, p, v, ws: Workspace, n_iter: int, stream=None):
+    """geo_step with HIP events around the fused sweep only: returns
+    (geo_result, summed milliseconds of that kernel)."""
+    out = geo_result()
+    ms = ctypes.c_double()
+    _check(lib().geo_step_timed(dims, ctypes.byref(p), _f32(v), ws.ptr, ws.nbytes, int(n_iter),
+                                _stream(stream), ctypes.byref(out), ctypes.byref(ms)),
+           "geo_step_timed", allow_maxiter=True)
+    return out, ms.value
 
 
 def geo_solve(dims, p, v, u, s, t, ws: Workspace, stream=None) -> geo_result:

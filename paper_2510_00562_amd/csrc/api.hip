@@ -161,10 +161,12 @@ int geo_state_init(geo_dims dims, const geo_params *p, const float *v, void *ws,
 // radix levels of a threshold search whose predicted window missed. The
 // loop tops up slots until every cube has done n_iter iterations (the device
 // idles a cube after them) or met its stopping rule.
+// phase_ms (may be null): nph = GEO_NPHASE phase times (4 events per slot),
+// or nph = 1 for sweep A alone (2 events per slot).
 static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const float *const *v,
                      void *const *ws, const size_t *ws_bytes, void *table, size_t table_bytes,
                      int32_t n_iter, int use_graph, hipStream_t st, geo_result *out,
-                     double *phase_ms)
+                     double *phase_ms, int nph = GEO_NPHASE)
 {
     if (n < 1 || n > kMaxBatch || !dims || !p || !v || !ws || !ws_bytes || n_iter < 0)
         return GEO_EINVAL;
@@ -192,8 +194,9 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
     for (int c = 0; c < n && !rc; ++c)
         rc = hip_status(launch_begin_call(ws[c], L[c], p[c].tol, p[c].alpha, p[c].beta, n_iter, st));
     if (rc) return rc;
+    const int nev = nph == 1 ? 2 : 4;
     if (phase_ms)
-        for (int q = 0; q < GEO_NPHASE; ++q) phase_ms[q] = 0.0;
+        for (int q = 0; q < nph; ++q) phase_ms[q] = 0.0;
     bool any_tol = false;
     for (int c = 0; c < n; ++c) any_tol = any_tol || p[c].tol > 0.0;
     const int every = p[0].check_every > 0 ? p[0].check_every : 32;
@@ -221,7 +224,7 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
     while (!rc) {
         const int batch = (any_tol && behind > every) ? every : behind;
         if (phase_ms) {
-            const size_t need = (size_t)4 * batch;
+            const size_t need = (size_t)nev * batch;
             while (ev.size() < need && !rc) {
                 hipEvent_t e;
                 rc = hip_status(hipEventCreate(&e));
@@ -232,7 +235,8 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
             if (gexec)
                 rc = hip_status(hipGraphLaunch(gexec, st));
             else
-                rc = hip_status(launch_slot(table, L[0].dual_bytes, sh, st, phase_ms ? &ev[4 * q] : nullptr));
+                rc = hip_status(launch_slot(table, L[0].dual_bytes, sh, st,
+                                            phase_ms ? &ev[(size_t)nev * q] : nullptr, nev));
         }
         for (int c = 0; c < n && !rc; ++c)
             rc = hip_status(hipMemcpyAsync(&sc[c], (const char *)ws[c] + L[c].scalars, sizeof(DevScalars),
@@ -240,9 +244,10 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         if (!rc) rc = hip_status(hipStreamSynchronize(st));
         if (!rc && phase_ms)
             for (int q = 0; q < batch && !rc; ++q)
-                for (int ph = 0; ph < GEO_NPHASE && !rc; ++ph) {
+                for (int ph = 0; ph < nph && !rc; ++ph) {
                     float ms = 0.f;
-                    rc = hip_status(hipEventElapsedTime(&ms, ev[4 * q + ph], ev[4 * q + ph + 1]));
+                    rc = hip_status(hipEventElapsedTime(&ms, ev[(size_t)nev * q + ph],
+                                                        ev[(size_t)nev * q + ph + 1]));
                     phase_ms[ph] += ms;
                 }
         behind = 0;
@@ -279,7 +284,8 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
 }
 
 static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
-                     int32_t n_iter, void *stream, geo_result *out, double *phase_ms)
+                     int32_t n_iter, void *stream, geo_result *out, double *phase_ms,
+                     int nph = GEO_NPHASE)
 {
     if (!dims_ok(dims) || !params_ok(p) || !v || n_iter < 0) return GEO_EINVAL;
     Layout L;
@@ -287,7 +293,7 @@ static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *w
     if (rc) return rc;
     void *table = (char *)ws + L.table;
     return run_cubes(1, &dims, p, &v, &ws, &ws_bytes, table, sizeof(CubeEntry), n_iter, 0, S(stream),
-                     out, phase_ms);
+                     out, phase_ms, nph);
 }
 
 int geo_step(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
@@ -301,6 +307,13 @@ int geo_step_profiled(geo_dims dims, const geo_params *p, const float *v, void *
 {
     if (!phase_ms) return GEO_EINVAL;
     return step_impl(dims, p, v, ws, ws_bytes, n_iter, stream, out, phase_ms);
+}
+
+int geo_step_timed(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
+                   int32_t n_iter, void *stream, geo_result *out, double *sweep_a_ms)
+{
+    if (!sweep_a_ms) return GEO_EINVAL;
+    return step_impl(dims, p, v, ws, ws_bytes, n_iter, stream, out, sweep_a_ms, 1);
 }
 
 int geo_solve(geo_dims dims, const geo_params *p, const float *v, float *u, float *s, float *t,

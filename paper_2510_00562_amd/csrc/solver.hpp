@@ -234,10 +234,11 @@ void cube_entry(CubeEntry *e, const Dims &d, const float *v, void *ws, const Lay
                 double mu_lo, double mu_hi, int kc, int tile0, int b0, int *ntiles, int *nb);
 int sweep_a_grid(int dual_bytes, int total_tiles);
 // One launch slot over the table (device copy of the entries). ev (may be
-// null): 4 events recorded at the phase boundaries (before sweep A, after
-// sweep A, after the threshold search, after sweep B and the finalize).
+// null): nev = 4 events recorded at the phase boundaries (before sweep A,
+// after sweep A, after the threshold search, after sweep B and the
+// finalize), or nev = 2 around sweep A only.
 hipError_t launch_slot(const void *table, int dual_bytes, const LaunchShape &sh, hipStream_t st,
-                       hipEvent_t *ev = nullptr);
+                       hipEvent_t *ev = nullptr, int nev = 4);
 // out != null: copy the variable out (FP32); otherwise load it from in.
 hipError_t launch_state_io(const Dims &d, void *ws, const Layout &L, int var, const float *v,
                            float *out, const float *in, hipStream_t st);

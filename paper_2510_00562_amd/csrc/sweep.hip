@@ -865,19 +865,19 @@ void cube_entry_t(CubeArgs<DT> *a, const Dims &d, const float *v, void *ws, cons
 }
 
 template <typename DT>
-hipError_t slot_t(const void *table, const LaunchShape &sh, hipStream_t st, hipEvent_t *ev)
+hipError_t slot_t(const void *table, const LaunchShape &sh, hipStream_t st, hipEvent_t *ev, int nev)
 {
     const CubeArgs<DT> *cubes = (const CubeArgs<DT> *)table;
     const int stride = (int)sizeof(CubeArgs<DT>);
-    if (ev) (void)hipEventRecord(ev[0], st);
+    if (nev >= 2) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(k_sweep_a<DT>, dim3(sh.grid_a), dim3(NT), 0, st, cubes, sh);
-    if (ev) (void)hipEventRecord(ev[1], st);
+    if (nev >= 2) (void)hipEventRecord(ev[1], st);
     hipError_t e = launch_select_window(table, stride, sh.ncubes, st);
     if (e != hipSuccess) return e;
-    if (ev) (void)hipEventRecord(ev[2], st);
+    if (nev >= 4) (void)hipEventRecord(ev[2], st);
     hipLaunchKernelGGL(k_sweep_b<DT>, dim3(sh.total_b), dim3(NPT), 0, st, cubes, sh);
     hipLaunchKernelGGL(k_finalize, dim3(sh.ncubes), dim3(NPT), 0, st, (const char *)table, stride);
-    if (ev) (void)hipEventRecord(ev[3], st);
+    if (nev >= 4) (void)hipEventRecord(ev[3], st);
     return hipGetLastError();
 }
 
@@ -904,9 +904,10 @@ int sweep_a_grid(int dual_bytes, int total_tiles)
 }
 
 hipError_t launch_slot(const void *table, int dual_bytes, const LaunchShape &sh, hipStream_t st,
-                       hipEvent_t *ev)
+                       hipEvent_t *ev, int nev)
 {
-    return dual_bytes == 2 ? slot_t<bf16>(table, sh, st, ev) : slot_t<float>(table, sh, st, ev);
+    if (!ev) nev = 0;
+    return dual_bytes == 2 ? slot_t<bf16>(table, sh, st, ev, nev) : slot_t<float>(table, sh, st, ev, nev);
 }
 
 hipError_t launch_init(const Dims &d, const float *v, void *ws, const Layout &L, double eps,
