@@ -38,8 +38,12 @@ def test_strerror_and_argument_checks_without_gpu():
     n = ctypes.c_size_t()
     assert L.geo_workspace_size(geo.geo_dims(0, 4, 4), None, ctypes.byref(n)) == -1
     assert L.geo_workspace_size(geo.geo_dims(64, 64, 16), None, ctypes.byref(n)) == 0
-    # 21 state planes twice, plus y4', z_s, z_t: at least 45 words per voxel
-    assert n.value >= 45 * 4 * 64 * 64 * 16
+    # 21 state planes twice, plus the y4 intermediate: at least 43 words per voxel
+    assert n.value >= 43 * 4 * 64 * 64 * 16
+    # batch argument checks need no device
+    assert L.geo_batch_table_size(0, ctypes.byref(n)) == -1
+    assert L.geo_batch_table_size(65, ctypes.byref(n)) == -1
+    assert L.geo_batch_table_size(3, ctypes.byref(n)) == 0 and n.value % 256 == 0
     p = geo.params(1.0, 1.0, 1.0, mu_lo=1.0, mu_hi=0.0)
     assert L.geo_state_init(geo.geo_dims(4, 4, 4), ctypes.byref(p), None, None, 0, None) == -1
     p = geo.params(1.0, 1.0, 1.0)
