@@ -293,9 +293,9 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
                 const uint32_t q = vox32(kk, oi, oj);
                 ru_u = src.u[q];
                 ru_y4 = ld(src.y4 + q);
-                ru_v = a.c.v[q];
-                ru_s = src.s[q];
-                ru_t = src.t[q];
+                ru_v = ld_nt(a.c.v + q);
+                ru_s = ld_nt(src.s + q);
+                ru_t = ld_nt(src.t + q);
                 ru_y3c = oi <= n1 - 2 ? ld(src.y3 + q) : 0.f;
                 ru_y3m = oi >= 1 ? ld(src.y3 + q - n2) : 0.f;
             }
@@ -351,9 +351,9 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
                 if (own_band) {
                     wr = true;
                     const uint32_t q = vox32(kk, oi, oj);
-                    dst.u[q] = un;
+                    st_nt(dst.u + q, un);
                     // 5 (y4 + u'/5) - v: step 14 without s', t', times 5, minus v
-                    st(a.y4p + q, (5.f * y4 + up) - ru_v);
+                    st_nt(a.y4p + q, (5.f * y4 + up) - ru_v);
                     const float dl = un - ru_u;
                     du2 += (double)(dl * dl);
                     u2 += (double)(ru_u * ru_u);
@@ -428,7 +428,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
                         const uint32_t q = vox32(k, i, j);
                         float2 *wd = f ? dst.w2 : dst.w1;
 #pragma unroll
-                        for (int g = 0; g < 3; ++g) (wd + (size_t)g * N)[q] = make_float2(wn[2 * g], wn[2 * g + 1]);
+                        for (int g = 0; g < 3; ++g) st_nt(wd + (size_t)g * N + q, make_float2(wn[2 * g], wn[2 * g + 1]));
                     }
 #pragma unroll
                     for (int cc = 0; cc < 6; ++cc) o6[cc] = 2.f * wn[cc] - wo[cc];
@@ -484,7 +484,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
                 }
                 const float gv = f ? msk * (dn_v - du_v) : du_v;
                 const float gh = f ? msk * (dn_h - du_h) : du_h;
-                st2(yd + q, make_float2(y.x + kStepY * (gv - pv), y.y + kStepY * (gh - ph)));
+                st2_nt(yd + q, make_float2(y.x + kStepY * (gv - pv), y.y + kStepY * (gh - ph)));
             }
         };
 
@@ -586,8 +586,8 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh
             y4[r] = in ? y4_of(ld(src.y4 + q), a4) : 0.f;
             to[r] = in ? src.t[q] : 0.f;
             if (r < RB) {
-                so[r] = in ? src.s[q] : 0.f;
-                yp[r] = in ? ld(a.y4p + q) : 0.f;
+                so[r] = in ? ld_nt(src.s + q) : 0.f;
+                yp[r] = in ? ld_nt(a.y4p + q) : 0.f;
             }
         }
         float tp[RB + 1];
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh
             const float y3m = r == 0 ? y3m0 : y3r[r - 1];
             const float tn = soft(zt_of(to[r], y3m, i <= n1 - 2 ? y3r[r] : 0.f, y4[r]), tt);
             tp[r] = 2.f * tn - to[r];
-            if (r < RB && i < n1) dst.t[q0 + (uint32_t)(r * n2)] = tn;
+            if (r < RB && i < n1) st_nt(dst.t + q0 + (uint32_t)(r * n2), tn);
         }
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
@@ -607,11 +607,11 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh
                 const float sn = soft(zs_of(so[r], y4[r]), ts);
                 const float sp = 2.f * sn - so[r];
                 const float tp1 = i <= n1 - 2 ? tp[r + 1] : 0.f;
-                dst.s[q] = sn;
-                st(dst.y3 + q, y3r[r] + kStepY * mask_le(i, n1) * (tp1 - tp[r]));
+                st_nt(dst.s + q, sn);
+                st_nt(dst.y3 + q, y3r[r] + kStepY * mask_le(i, n1) * (tp1 - tp[r]));
                 // q+ = 5 y4' - v (step 14); r = ||q+|| (step 15)
                 const float qn = as_stored(dst.y4, yp[r] + (sp + tp[r]));
-                st(dst.y4 + q, qn);
+                st_nt(dst.y4 + q, qn);
                 r2 += (double)qn * (double)qn;
             }
         }
