@@ -540,12 +540,150 @@ __device__ __forceinline__ float soft(float z, double tau)
     return m > 0.0 ? copysignf((float)m, z) : 0.0f;
 }
 
+constexpr int RB = GEO_SWEEP_B_ROWS;  // rows per sweep B strip
+// CPT consecutive values of one row: one 4- or 8-byte access for a pair.
+__device__ __forceinline__ void ldv(const float *p, float (&o)[1]) { o[0] = *p; }
+__device__ __forceinline__ void ldv(const bf16 *p, float (&o)[1]) { o[0] = ld(p); }
+__device__ __forceinline__ void ldv(const float *p, float (&o)[2])
+{
+    const float2 x = *reinterpret_cast<const float2 *>(p);
+    o[0] = x.x;
+    o[1] = x.y;
+}
+__device__ __forceinline__ void ldv(const bf16 *p, float (&o)[2])
+{
+    const float2 x = ld2(reinterpret_cast<const bf16x2 *>(p));
+    o[0] = x.x;
+    o[1] = x.y;
+}
+__device__ __forceinline__ void ldv_nt(const float *p, float (&o)[1]) { o[0] = ld_nt(p); }
+__device__ __forceinline__ void ldv_nt(const bf16 *p, float (&o)[1]) { o[0] = ld_nt(p); }
+__device__ __forceinline__ void ldv_nt(const float *p, float (&o)[2])
+{
+#if GEO_NT_LOADS
+    const f32x2 x = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(p));
+    o[0] = x.x;
+    o[1] = x.y;
+#else
+    ldv(p, o);
+#endif
+}
+__device__ __forceinline__ void ldv_nt(const bf16 *p, float (&o)[2])
+{
+#if GEO_NT_LOADS
+    const uint32_t b = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(p));
+    o[0] = __uint_as_float(b << 16);
+    o[1] = __uint_as_float(b & 0xffff0000u);
+#else
+    ldv(p, o);
+#endif
+}
+template <typename T>
+__device__ __forceinline__ void stv_nt(T *p, const float (&x)[1]) { st_nt(p, x[0]); }
+__device__ __forceinline__ void stv_nt(float *p, const float (&x)[2])
+{
+    st_nt(reinterpret_cast<float2 *>(p), make_float2(x[0], x[1]));
+}
+__device__ __forceinline__ void stv_nt(bf16 *p, const float (&x)[2])
+{
+    st2_nt(reinterpret_cast<bf16x2 *>(p), make_float2(x[0], x[1]));
+}
+
 // Steps 2, 3 (soft thresholds at the selected levels), 7, 8, 13 and 14; the
 // z inputs are evaluated again exactly as sweep A did. A thread takes a strip
-// of RB rows of one (band, column) and issues all of its loads at once; only
-// the rows just above and below the strip (D_v coupling of t' and y3) are
-// read twice.
-constexpr int RB = GEO_SWEEP_B_ROWS;
+// of RB rows and CPT adjacent columns of one band and issues all of its loads
+// at once; only the rows just above and below the strip (D_v coupling of t'
+// and y3) are read twice. CPT = 2 (one access per pair) when the row length
+// is even, else 1.
+template <typename DT, int CPT>
+__device__ __forceinline__ double sweep_b_strips(const CubeArgs<DT> &a, const DevScalars *sc, int lb)
+{
+    const Dims d = a.c.d;
+    const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
+    const int par = (int)(sc->iter & 1u);
+    const Side<DT> src = a.side[par], dst = a.side[par ^ 1];
+    const float a4 = (float)sc->a4;
+    const double ts = sc->sel[0].tau, tt = sc->sel[1].tau;
+    double r2 = 0.0;
+    const uint32_t nstrip = (uint32_t)((n1 + RB - 1) / RB);
+    const uint32_t ncol = (uint32_t)(n2 / CPT);
+    const uint32_t items = (uint32_t)n3 * nstrip * ncol;
+    const uint32_t stride = (uint32_t)a.c.nb * NPT;
+    for (uint32_t w = (uint32_t)lb * NPT + threadIdx.x; w < items; w += stride) {
+        const uint32_t j = CPT * (w % ncol), rr = w / ncol;
+        const int ia = (int)(rr % nstrip) * RB, k = (int)(rr / nstrip);
+        const uint32_t q0 = ((uint32_t)k * (uint32_t)n1 + (uint32_t)ia) * (uint32_t)n2 + j;
+        // rows ia .. ia+RB-1 of the strip, and row ia+RB for the D_v coupling
+        float y3r[RB + 1][CPT], y4[RB + 1][CPT], to[RB + 1][CPT], so[RB][CPT], yp[RB][CPT];
+        float y3m0[CPT];
+        if (ia >= 1) ldv(src.y3 + q0 - n2, y3m0);
+        else
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) y3m0[c] = 0.f;
+#pragma unroll
+        for (int r = 0; r <= RB; ++r) {
+            const bool in = ia + r < n1;
+            const uint32_t q = q0 + (uint32_t)(r * n2);
+            float q4[CPT];
+            if (in) {
+                ldv(src.y3 + q, y3r[r]);
+                ldv(src.y4 + q, q4);
+                ldv(src.t + q, to[r]);
+                if (r < RB) {
+                    ldv_nt(src.s + q, so[r]);
+                    ldv_nt(a.y4p + q, yp[r]);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    y3r[r][c] = q4[c] = to[r][c] = 0.f;
+                    if (r < RB) so[r][c] = yp[r][c] = 0.f;
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) y4[r][c] = in ? y4_of(q4[c], a4) : 0.f;
+        }
+        float tp[RB + 1][CPT];
+#pragma unroll
+        for (int r = 0; r <= RB; ++r) {
+            const int i = ia + r;
+            float tn[CPT];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const float y3m = r == 0 ? y3m0[c] : y3r[r - 1][c];
+                tn[c] = soft(zt_of(to[r][c], y3m, i <= n1 - 2 ? y3r[r][c] : 0.f, y4[r][c]), tt);
+                tp[r][c] = 2.f * tn[c] - to[r][c];
+            }
+            if (r < RB && i < n1) stv_nt(dst.t + q0 + (uint32_t)(r * n2), tn);
+        }
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const int i = ia + r;
+            if (i < n1) {
+                const uint32_t q = q0 + (uint32_t)(r * n2);
+                float sn[CPT], y3n[CPT], qn[CPT];
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    sn[c] = soft(zs_of(so[r][c], y4[r][c]), ts);
+                    const float sp = 2.f * sn[c] - so[r][c];
+                    const float tp1 = i <= n1 - 2 ? tp[r + 1][c] : 0.f;
+                    y3n[c] = y3r[r][c] + kStepY * mask_le(i, n1) * (tp1 - tp[r][c]);
+                    // q+ = 5 y4' - v (step 14); r = ||q+|| (step 15)
+                    qn[c] = as_stored(dst.y4, yp[r][c] + (sp + tp[r][c]));
+                    r2 += (double)qn[c] * (double)qn[c];
+                }
+                stv_nt(dst.s + q, sn);
+                stv_nt(dst.y3 + q, y3n);
+                stv_nt(dst.y4 + q, qn);
+            }
+        }
+    }
+    return r2;
+}
+
+// Columns per sweep B thread for a row length.
+__host__ __device__ inline int sweep_b_cpt(int n2) { return (n2 & 1) ? 1 : 2; }
+
 template <typename DT>
 __global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh)
 {
@@ -558,66 +696,13 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh
     }
     __syncthreads();
     const CubeArgs<DT> &a = cubes[__builtin_amdgcn_readfirstlane(cube_of_block)];
-    DevScalars *sc = a.c.sc;
+    const DevScalars *sc = a.c.sc;
     if (idle(sc) || !(sc->sel[0].done && sc->sel[1].done)) return;
     const int lb = (int)blockIdx.x - a.c.b0;  // block within the cube
-    const Dims d = a.c.d;
-    const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
-    const int par = (int)(sc->iter & 1u);
-    const Side<DT> src = a.side[par], dst = a.side[par ^ 1];
-    const float a4 = (float)sc->a4;
-    const double ts = sc->sel[0].tau, tt = sc->sel[1].tau;
-    double r2 = 0.0;
-    const uint32_t nstrip = (uint32_t)((n1 + RB - 1) / RB);
-    const uint32_t items = (uint32_t)n3 * nstrip * (uint32_t)n2;
-    const uint32_t stride = (uint32_t)a.c.nb * NPT;
-    for (uint32_t w = (uint32_t)lb * NPT + threadIdx.x; w < items; w += stride) {
-        const uint32_t j = w % (uint32_t)n2, rr = w / (uint32_t)n2;
-        const int ia = (int)(rr % nstrip) * RB, k = (int)(rr / nstrip);
-        const uint32_t q0 = ((uint32_t)k * (uint32_t)n1 + (uint32_t)ia) * (uint32_t)n2 + j;
-        // rows ia .. ia+RB-1 of the strip, and row ia+RB for the D_v coupling
-        float y3r[RB + 1], y4[RB + 1], to[RB + 1], so[RB], yp[RB];
-        const float y3m0 = ia >= 1 ? ld(src.y3 + q0 - n2) : 0.f;
-#pragma unroll
-        for (int r = 0; r <= RB; ++r) {
-            const bool in = ia + r < n1;
-            const uint32_t q = q0 + (uint32_t)(r * n2);
-            y3r[r] = in ? ld(src.y3 + q) : 0.f;
-            y4[r] = in ? y4_of(ld(src.y4 + q), a4) : 0.f;
-            to[r] = in ? src.t[q] : 0.f;
-            if (r < RB) {
-                so[r] = in ? ld_nt(src.s + q) : 0.f;
-                yp[r] = in ? ld_nt(a.y4p + q) : 0.f;
-            }
-        }
-        float tp[RB + 1];
-#pragma unroll
-        for (int r = 0; r <= RB; ++r) {
-            const int i = ia + r;
-            const float y3m = r == 0 ? y3m0 : y3r[r - 1];
-            const float tn = soft(zt_of(to[r], y3m, i <= n1 - 2 ? y3r[r] : 0.f, y4[r]), tt);
-            tp[r] = 2.f * tn - to[r];
-            if (r < RB && i < n1) st_nt(dst.t + q0 + (uint32_t)(r * n2), tn);
-        }
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const int i = ia + r;
-            if (i < n1) {
-                const uint32_t q = q0 + (uint32_t)(r * n2);
-                const float sn = soft(zs_of(so[r], y4[r]), ts);
-                const float sp = 2.f * sn - so[r];
-                const float tp1 = i <= n1 - 2 ? tp[r + 1] : 0.f;
-                st_nt(dst.s + q, sn);
-                st_nt(dst.y3 + q, y3r[r] + kStepY * mask_le(i, n1) * (tp1 - tp[r]));
-                // q+ = 5 y4' - v (step 14); r = ||q+|| (step 15)
-                const float qn = as_stored(dst.y4, yp[r] + (sp + tp[r]));
-                st_nt(dst.y4 + q, qn);
-                r2 += (double)qn * (double)qn;
-            }
-        }
-    }
-    r2 = block_sum<NPT>(r2, red);
-    if (threadIdx.x == 0) a.c.part[2 * a.c.ntiles + lb] = r2;
+    const double r2 = sweep_b_cpt(a.c.d.n2) == 2 ? sweep_b_strips<DT, 2>(a, sc, lb)
+                                                  : sweep_b_strips<DT, 1>(a, sc, lb);
+    const double tot = block_sum<NPT>(r2, red);
+    if (threadIdx.x == 0) a.c.part[2 * a.c.ntiles + lb] = tot;
 }
 
 // Fixed-order sums of the block partials of both sweeps: relative change of u
@@ -848,8 +933,9 @@ void cube_entry_t(CubeArgs<DT> *a, const Dims &d, const float *v, void *ws, cons
     c.capt = (int)(L.cap / c.ntiles);
     c.tile0 = tile0;
     {
-        // strips of RB rows; never more blocks than the partials hold
-        const int64_t items = (int64_t)d.n3 * ((d.n1 + RB - 1) / RB) * d.n2;
+        // strips of RB rows and CPT columns; never more blocks than the
+        // partials hold
+        const int64_t items = (int64_t)d.n3 * ((d.n1 + RB - 1) / RB) * (d.n2 / sweep_b_cpt(d.n2));
         const int pb = point_blocks(items);
         c.nb = pb < kSweepBBlocks ? pb : kSweepBBlocks;
     }
