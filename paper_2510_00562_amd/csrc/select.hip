@@ -490,9 +490,60 @@ __device__ void level_step(SelState *sel, Hist *hist, int f)
         }
 }
 
-// One block per (cube, field) of a launch table: block 2c + f.
-__global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table, int stride)
+#ifndef GEO_PREFETCH_BUDGET
+#define GEO_PREFETCH_BUDGET 128  // MB: half the memory-side cache
+#endif
+#ifndef GEO_PREFETCH_MASK
+#define GEO_PREFETCH_MASK 31  // s, t, y3, y4, the y4 intermediate
+#endif
+// Blocks past the search's read sweep B's inputs once, so that sweep B finds
+// them in the memory-side cache (the search itself keeps only two CUs per
+// cube busy). The values are consumed by an empty asm statement only.
+__device__ void prefetch_sweep_b_inputs(const char *table, int stride, int ncubes, int pb, int np)
 {
+    // at most GEO_PREFETCH_BUDGET MB in all: the leading part of every array,
+    // which is what sweep B's first grid-stride rounds read
+    double total = 0.0;
+    for (int c = 0; c < ncubes; ++c) {
+        const CubeCommon &cc = *reinterpret_cast<const CubeCommon *>(table + (size_t)c * stride);
+        if (idle(cc.sc)) continue;
+        for (int a = 0; a < 5; ++a)
+            if ((GEO_PREFETCH_MASK >> a) & 1) total += (double)cc.bin_bytes[a];
+    }
+    const double frac = total > 0.0 ? fmin(1.0, GEO_PREFETCH_BUDGET * 1048576.0 / total) : 0.0;
+    for (int c = 0; c < ncubes; ++c) {
+        const CubeCommon &cc = *reinterpret_cast<const CubeCommon *>(table + (size_t)c * stride);
+        const DevScalars *sc = cc.sc;
+        if (idle(sc)) continue;
+        const int par = (int)(sc->iter & 1u);
+        for (int a = 0; a < 5; ++a) {
+            if (!((GEO_PREFETCH_MASK >> a) & 1)) continue;
+            const uint4 *p = reinterpret_cast<const uint4 *>(cc.bin[par][a]);
+            const size_t n16 = (size_t)(frac * (double)(cc.bin_bytes[a] / 16));
+            const size_t stride16 = (size_t)np * kWinThreads;
+            for (size_t i = (size_t)pb * kWinThreads + threadIdx.x; i < n16; i += 4 * stride16) {
+                uint4 x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const size_t k = i + u * stride16;
+                    x[u] = k < n16 ? p[k] : make_uint4(0u, 0u, 0u, 0u);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u) asm volatile("" ::"v"(x[u].x));
+            }
+        }
+    }
+}
+
+// One block per (cube, field) of a launch table: block 2c + f; blocks past
+// 2 * ncubes prefetch.
+__global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table, int stride, int ncubes)
+{
+    if ((int)blockIdx.x >= 2 * ncubes) {
+        prefetch_sweep_b_inputs(table, stride, ncubes, (int)blockIdx.x - 2 * ncubes,
+                                (int)gridDim.x - 2 * ncubes);
+        return;
+    }
     const CubeCommon &cc = *reinterpret_cast<const CubeCommon *>(table + (size_t)(blockIdx.x >> 1) * stride);
     const int f = blockIdx.x & 1;
     DevScalars *sc = cc.sc;
@@ -798,10 +849,11 @@ hipError_t select_run(const float *z0, const float *z1, int nfields, int64_t n, 
     return hipGetLastError();
 }
 
-hipError_t launch_select_window(const void *table, int stride, int ncubes, hipStream_t st)
+hipError_t launch_select_window(const void *table, int stride, int ncubes, int prefetch_blocks,
+                                hipStream_t st)
 {
-    hipLaunchKernelGGL(k_select_window, dim3(2 * ncubes), dim3(kWinThreads), 0, st,
-                       (const char *)table, stride);
+    hipLaunchKernelGGL(k_select_window, dim3(2 * ncubes + prefetch_blocks), dim3(kWinThreads), 0, st,
+                       (const char *)table, stride, ncubes);
     return hipGetLastError();
 }
 

@@ -169,6 +169,10 @@ struct CubeCommon {
     int b0, nb;         // sweep B blocks of this cube: first, count
     float thr1;         // omega * step of w1
     float mu_lo, mu_hi;
+    // sweep B's inputs by side parity (s, t, y3, y4, the y4 intermediate)
+    // and their sizes, for the cache prefetch that runs beside the search
+    const void *bin[2][5];
+    size_t bin_bytes[5];
 };
 template <typename DT>
 struct CubeArgs {
@@ -256,7 +260,10 @@ hipError_t launch_l1_threshold(const float *x, int64_t n, double radius, SelStat
 hipError_t launch_soft(const float *x, int64_t n, const SelState *sel, float *out, hipStream_t st);
 // The solver's per-iteration search over a table of cubes (entries of
 // `stride` bytes, CubeCommon first): one block per (cube, field).
-hipError_t launch_select_window(const void *table, int stride, int ncubes, hipStream_t st);
+// Extra blocks of the same launch stream sweep B's inputs through the
+// memory-side cache meanwhile (prefetch_blocks, 0 = none).
+hipError_t launch_select_window(const void *table, int stride, int ncubes, int prefetch_blocks,
+                                hipStream_t st);
 
 // Standalone projections (ops.hip).
 int l2_blocks(int64_t n);

@@ -541,6 +541,10 @@ __device__ __forceinline__ float soft(float z, double tau)
 }
 
 constexpr int RB = GEO_SWEEP_B_ROWS;  // rows per sweep B strip
+#ifndef GEO_PREFETCH_BLOCKS
+#define GEO_PREFETCH_BLOCKS 240
+#endif
+constexpr int kPrefetchBlocks = GEO_PREFETCH_BLOCKS;  // cache prefetch beside the search
 // CPT consecutive values of one row: one 4- or 8-byte access for a pair.
 __device__ __forceinline__ void ldv(const float *p, float (&o)[1]) { o[0] = *p; }
 __device__ __forceinline__ void ldv(const bf16 *p, float (&o)[1]) { o[0] = ld(p); }
@@ -946,6 +950,16 @@ void cube_entry_t(CubeArgs<DT> *a, const Dims &d, const float *v, void *ws, cons
     a->side[0] = side_of<DT>(ws, L, 0);
     a->side[1] = side_of<DT>(ws, L, 1);
     a->y4p = (DT *)(b + L.y4p);
+    for (int p = 0; p < 2; ++p) {
+        c.bin[p][0] = a->side[p].s;
+        c.bin[p][1] = a->side[p].t;
+        c.bin[p][2] = a->side[p].y3;
+        c.bin[p][3] = a->side[p].y4;
+        c.bin[p][4] = a->y4p;
+    }
+    const size_t N = (size_t)d.plane;
+    c.bin_bytes[0] = c.bin_bytes[1] = N * sizeof(float);
+    c.bin_bytes[2] = c.bin_bytes[3] = c.bin_bytes[4] = N * sizeof(DT);
     *ntiles = c.ntiles;
     *nb = c.nb;
 }
@@ -958,7 +972,7 @@ hipError_t slot_t(const void *table, const LaunchShape &sh, hipStream_t st, hipE
     if (nev >= 2) (void)hipEventRecord(ev[0], st);
     hipLaunchKernelGGL(k_sweep_a<DT>, dim3(sh.grid_a), dim3(NT), 0, st, cubes, sh);
     if (nev >= 2) (void)hipEventRecord(ev[1], st);
-    hipError_t e = launch_select_window(table, stride, sh.ncubes, st);
+    hipError_t e = launch_select_window(table, stride, sh.ncubes, kPrefetchBlocks, st);
     if (e != hipSuccess) return e;
     if (nev >= 4) (void)hipEventRecord(ev[2], st);
     hipLaunchKernelGGL(k_sweep_b<DT>, dim3(sh.total_b), dim3(NPT), 0, st, cubes, sh);
