@@ -324,6 +324,9 @@ def bench_serve(args):
     done = rep.pop("jobs")
     mean_vox = float(np.mean([j.v.size for j in done]))
     offered = args.rate * mean_vox * rep["mean_iterations"]
+    # the rate one GPU sustains at the throughput the loop reached: requests
+    # per second whose work (mean voxels x mean iterations) it can absorb
+    sustainable = rep["voxel_iterations_per_s"] / (mean_vox * rep["mean_iterations"])
     out = {
         "metric": "P-PDS request loop latency",
         "value": rep["latency_p50_s"],
@@ -343,6 +346,8 @@ def bench_serve(args):
         "mean_iterations": rep["mean_iterations"],
         "converged": rep["converged"],
         "offered_voxel_iterations_per_s": offered,
+        "rho": offered / rep["voxel_iterations_per_s"],
+        "sustainable_requests_per_s": sustainable,
         "span_s": rep["span_s"],
     }
     print(json.dumps(out), flush=True)
