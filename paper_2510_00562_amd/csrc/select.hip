@@ -576,12 +576,39 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
     __shared__ int nshift, nnb;
     __shared__ double nS, nC;
     const int tid = threadIdx.x;
+    // the tile partials and candidate counts of sweep A (fixed order) do not
+    // depend on the search state: their loads go out together with it
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    uint32_t mine = 0u, cbs[kMaxTiles / kWinThreads];  // this thread's consecutive slices
+    bool my_ovf = false;
+    const int per = (grid_a + kWinThreads - 1) / kWinThreads;
+    for (int b = tid; b < grid_a; b += kWinThreads) {
+        const double *w = winpart + ((int64_t)f * grid_a + b) * 3;
+        a0 += w[0];
+        a1 += w[1];
+        a2 += w[2];
+    }
+#pragma unroll
+    for (int q = 0; q < kMaxTiles / kWinThreads; ++q) {
+        const int b = per * tid + q;
+        uint32_t cb = 0u;
+        if (q < per && b < grid_a) {
+            cb = ccount[(int64_t)f * grid_a + b];
+            if (cb > (uint32_t)capb) {
+                my_ovf = true;
+                cb = (uint32_t)capb;
+            }
+        }
+        cbs[q] = cb;
+        mine += cb;
+    }
     if (tid == 0) {
         s = sel[f];
         ovf = 0u;
         verdict = 0;
     }
     __syncthreads();
+    if (my_ovf) atomicOr(&ovf, 1u);  // read after the scans' barriers
     if (s.radius <= 0.0) {  // zero radius: the ball is {0}
         if (tid == 0) {
             SelState o = s;
@@ -594,24 +621,10 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         }
         return;
     }
-    // block partials of sweep A (fixed order) and the candidate slices
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    uint32_t mine = 0u;  // this thread's slice counts (per consecutive slices)
-    const int per = (grid_a + kWinThreads - 1) / kWinThreads;
-    for (int b = tid; b < grid_a; b += kWinThreads) {
-        const double *w = winpart + ((int64_t)f * grid_a + b) * 3;
-        a0 += w[0];
-        a1 += w[1];
-        a2 += w[2];
-    }
-    for (int b = per * tid; b < per * tid + per && b < grid_a; ++b) {
-        uint32_t cb = ccount[(int64_t)f * grid_a + b];
-        if (cb > (uint32_t)capb) {
-            atomicOr(&ovf, 1u);
-            cb = (uint32_t)capb;
-        }
-        pre[b] = cb;
-        mine += cb;
+#pragma unroll
+    for (int q = 0; q < kMaxTiles / kWinThreads; ++q) {
+        const int b = per * tid + q;
+        if (q < per && b < grid_a) pre[b] = cbs[q];
     }
     uint32_t all_c;
     const uint32_t off = block_exclusive_scan<uint32_t>(mine, wsu, all_c);
