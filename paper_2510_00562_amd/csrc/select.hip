@@ -829,10 +829,16 @@ __global__ __launch_bounds__(kSelThreads) void k_soft(const float *x, int64_t n,
 
 int hist_blocks(int64_t n)
 {
-    // small grid: in the solver these launches are no-ops unless the window
-    // missed, and an idle launch costs about its grid size
+    // 64 values per thread at most: the block histograms are flushed to
+    // global memory with atomics once per block
     int b = ceil_div(n, (int64_t)kSelThreads * 64);
-    return b < 1 ? 1 : (b > 96 ? 96 : b);
+    return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
+
+int soft_blocks(int64_t n)
+{
+    int b = ceil_div(n, (int64_t)kSelThreads * 4);
+    return b < 1 ? 1 : (b > 8192 ? 8192 : b);
 }
 
 }  // namespace
@@ -880,7 +886,7 @@ hipError_t launch_l1_threshold(const float *x, int64_t n, double radius, SelStat
 
 hipError_t launch_soft(const float *x, int64_t n, const SelState *sel, float *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_soft, dim3(hist_blocks(n)), dim3(kSelThreads), 0, st, x, n, sel, out);
+    hipLaunchKernelGGL(k_soft, dim3(soft_blocks(n)), dim3(kSelThreads), 0, st, x, n, sel, out);
     return hipGetLastError();
 }
 
