@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--requests", type=int, default=40, help="serve: requests in the stream")
     ap.add_argument("--rate", type=float, default=4.0, help="serve: Poisson arrivals per second")
     ap.add_argument("--hbm-budget-gb", type=float, default=96.0, help="serve: admission budget")
+    ap.add_argument("--active-mvoxels", type=float, default=16.0,
+                    help="serve: admit while fewer voxels than this (millions) are in flight; "
+                         "0 = by HBM footprint alone")
     ap.add_argument("--dual", choices=("f32", "bf16"), default="f32",
                     help="storage of the dual variables y1..y4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -320,7 +323,9 @@ def bench_serve(args):
         jobs.append(Job(q, np.ascontiguousarray(c["v"], dtype=np.float32), c["eps"], c["alpha"],
                         c["beta"], omega=c["omega"], tol=1e-4, cap=5000, arrival=arr))
     torch.cuda.synchronize()
-    rep = run_stream(jobs, int(args.hbm_budget_gb * 2 ** 30), round_iters=25, dual_storage=store)
+    cap = int(args.active_mvoxels * 1e6) if args.active_mvoxels > 0 else None
+    rep = run_stream(jobs, int(args.hbm_budget_gb * 2 ** 30), round_iters=25, dual_storage=store,
+                     active_voxels=cap)
     done = rep.pop("jobs")
     mean_vox = float(np.mean([j.v.size for j in done]))
     offered = args.rate * mean_vox * rep["mean_iterations"]
@@ -337,7 +342,8 @@ def bench_serve(args):
         "config": {"workload": f"{args.requests} requests, Poisson {args.rate}/s, sizes 128x128x64 / "
                                "256x256x128 / 256x256x190 / 512x512x224 (0.4/0.3/0.2/0.1), "
                                "tol 1e-4, cap 5000, FIFO admission by HBM footprint",
-                   "hbm_budget_gb": args.hbm_budget_gb, "dual_storage": args.dual},
+                   "hbm_budget_gb": args.hbm_budget_gb, "active_mvoxels": args.active_mvoxels,
+                   "dual_storage": args.dual},
         "latency_p50_s": rep["latency_p50_s"],
         "latency_p99_s": rep["latency_p99_s"],
         "latency_mean_s": rep["latency_mean_s"],

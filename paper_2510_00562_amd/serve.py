@@ -72,11 +72,18 @@ def footprint(shape, dual_storage: int = GEO_STORE_F32) -> int:
 
 
 class Server:
-    """Admission by HBM footprint, rounds of `round_iters` batched iterations."""
+    """Admission by HBM footprint, rounds of `round_iters` batched iterations.
+
+    active_voxels caps the work in flight: a waiting job is admitted only while
+    the admitted cubes hold fewer voxels than that (the first one always). The
+    GPU is full well before the HBM budget is, so admitting more only spreads
+    the same throughput over more jobs and delays every one of them. None
+    admits by footprint alone."""
 
     def __init__(self, hbm_budget: int, round_iters: int = 25, dual_storage: int = GEO_STORE_F32,
-                 use_graph: bool = True, clock=time.perf_counter):
+                 use_graph: bool = True, clock=time.perf_counter, active_voxels: int | None = None):
         self.budget = int(hbm_budget)
+        self.active_voxels = active_voxels
         self.round_iters = int(round_iters)
         self.dual_storage = dual_storage
         self.use_graph = use_graph
@@ -105,6 +112,9 @@ class Server:
             job = self.waiting[0]
             need = footprint(job.v.shape, self.dual_storage)
             if self.used + need > self.budget:
+                break
+            held = sum(a.vd.numel() for a in self.active)
+            if self.active_voxels is not None and self.active and held >= self.active_voxels:
                 break
             self.waiting.popleft()
             job.admitted = self.now()
@@ -151,11 +161,12 @@ class Server:
 
 
 def run_stream(jobs: list[Job], hbm_budget: int, round_iters: int = 25,
-               dual_storage: int = GEO_STORE_F32, use_graph: bool = True) -> dict:
+               dual_storage: int = GEO_STORE_F32, use_graph: bool = True,
+               active_voxels: int | None = None) -> dict:
     """Serve `jobs` (sorted by arrival, seconds from the start) in real time:
     each job is submitted when the clock reaches its arrival. Returns the
     finished jobs and the latency and throughput figures."""
-    srv = Server(hbm_budget, round_iters, dual_storage, use_graph)
+    srv = Server(hbm_budget, round_iters, dual_storage, use_graph, active_voxels=active_voxels)
     pending = deque(sorted(jobs, key=lambda j: j.arrival))
     done: list[Job] = []
     while pending or not srv.idle():
