@@ -2,7 +2,8 @@
 iterations of Alg. 1 on the 256 x 256 x 128 cube, in the launch
 configuration the benchmark times, against the FP64 oracle's run stored by
 tests/golden/make_long_runs.py (sampled u, s, t; MPSNR; last trace entry).
-Bounds: u within 1e-4 relative L2 on the samples, MPSNR within 0.01 dB."""
+Bounds: u, s and t within 1e-4 relative L2 on the samples, MPSNR within
+0.01 dB."""
 import json
 import os
 
@@ -46,5 +47,6 @@ def test_benchmark_cube_5000_iterations():
     print(f"u {eu:.2e}  s {es:.2e}  t {et:.2e}  band means {band:.2e}  MPSNR gap {gap:.2e} dB  "
           f"tau_s {res.tau_s:.6g}/{g['last_trace']['tau_s']:.6g}", flush=True)
     assert eu <= 1e-4 and band <= 1e-4
+    assert es <= 1e-4 and et <= 1e-4
     assert gap <= 0.01
     assert res.r == pytest.approx(g["last_trace"]["r"], rel=1e-4)
