@@ -91,6 +91,27 @@ def copy_probe():
     print("copy probe: 5 copies of 256 MiB", flush=True)
 
 
+def copy_ceiling():
+    """Bytes/s of a plain device copy (torch's copy kernel, 512 MiB read and
+    512 MiB written per launch, well beyond the 256 MB memory-side cache):
+    the streaming rate this chip reaches in practice, beside its 8 TB/s
+    peak. Mean of 10 launches after 2 untimed ones."""
+    import torch
+    a = torch.empty(128 * 1024 * 1024, dtype=torch.float32, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    for _ in range(2):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    sec = e0.elapsed_time(e1) / 1e3 / 10
+    del a, b
+    return 2 * 512 * 1024 * 1024 / sec
+
+
 def read_traffic(path, cube):
     """HBM bytes per launch of sweep A from the stored counter summary, or None
     when it is missing, for another cube, or taken from other kernel sources."""
@@ -191,6 +212,7 @@ def main():
     achieved = PB[dom] * N / avg_s
     traffic = (read_traffic(args.traffic, f"{n1}x{n2}x{n3}")
                if dom == "sweep_a" and db == 4 else None)
+    copy_bps = copy_ceiling()
     out = {
         "metric": "P-PDS voxel-iterations/s",
         "value": value,
@@ -213,7 +235,10 @@ def main():
                      "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": achieved / HBM_PEAK,
                      "traffic": traffic, "bytes_per_voxel": PB[dom],
                      "traffic_bytes_per_voxel": None if traffic is None else traffic / N,
-                     "avg_launch_ms": 1e3 * avg_s},
+                     "avg_launch_ms": 1e3 * avg_s,
+                     # the same figures against what a plain copy reaches
+                     "copy_ceiling": copy_bps / 1e9, "frac_of_copy": achieved / copy_bps,
+                     "traffic_rate": None if traffic is None else traffic / avg_s / 1e9},
         "iteration_hbm_frac": algo_bytes_iter(db) * value / HBM_PEAK,
         "phase_ms_per_step": {k: v_ / K for k, v_ in phase_ms.items()},
         "last": {"rel_change": res.rel_change, "r": res.r, "tau_s": res.tau_s,
