@@ -130,10 +130,13 @@ int geo_step_profiled(geo_dims dims, const geo_params *p, const float *v,
                       void *ws, size_t ws_bytes, int32_t n_iter, void *stream,
                       geo_result *out, double *phase_ms);
 
-/* geo_step with two HIP events per iteration around the fused sweep only
- * (its launch time for a roofline, at a fraction of geo_step_profiled's
- * event cost). *sweep_a_ms (host) receives the summed GPU time of that
- * kernel over the call. */
+/* geo_step with two HIP events around the fused sweep of every 8th
+ * iteration slot (the first of the call included), on `stream`: the
+ * kernel's launch time for a roofline. An event pair idles the GPU for a few
+ * microseconds, so sampling keeps that cost out of 7 of 8 iterations.
+ * *sweep_a_ms (host) receives the GPU time of that kernel summed over the
+ * call, estimated as the mean of the sampled launches times the number of
+ * slots. */
 int geo_step_timed(geo_dims dims, const geo_params *p, const float *v,
                    void *ws, size_t ws_bytes, int32_t n_iter, void *stream,
                    geo_result *out, double *sweep_a_ms);

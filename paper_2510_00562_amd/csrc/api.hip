@@ -161,8 +161,11 @@ int geo_state_init(geo_dims dims, const geo_params *p, const float *v, void *ws,
 // radix levels of a threshold search whose predicted window missed. The
 // loop tops up slots until every cube has done n_iter iterations (the device
 // idles a cube after them) or met its stopping rule.
-// phase_ms (may be null): nph = GEO_NPHASE phase times (4 events per slot),
-// or nph = 1 for sweep A alone (2 events per slot).
+// phase_ms (may be null): nph = GEO_NPHASE phase times (4 events in every
+// slot), or nph = 1 for sweep A alone: 2 events around it in every
+// kTimedEvery-th slot, the sampled times scaled to all slots (an event
+// pair costs a few microseconds of idle time between the launches it
+// brackets, which sampling keeps out of most iterations).
 static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const float *const *v,
                      void *const *ws, const size_t *ws_bytes, void *table, size_t table_bytes,
                      int32_t n_iter, int use_graph, hipStream_t st, geo_result *out,
@@ -195,6 +198,8 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         rc = hip_status(launch_begin_call(ws[c], L[c], p[c].tol, p[c].alpha, p[c].beta, n_iter, st));
     if (rc) return rc;
     const int nev = nph == 1 ? 2 : 4;
+    const int ev_every = nph == 1 ? kTimedEvery : 1;
+    long slots = 0, sampled = 0;
     if (phase_ms)
         for (int q = 0; q < nph; ++q) phase_ms[q] = 0.0;
     bool any_tol = false;
@@ -224,26 +229,31 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
     while (!rc) {
         const int batch = (any_tol && behind > every) ? every : behind;
         if (phase_ms) {
-            const size_t need = (size_t)nev * batch;
+            const size_t need = (size_t)nev * (batch / ev_every + 1);
             while (ev.size() < need && !rc) {
                 hipEvent_t e;
                 rc = hip_status(hipEventCreate(&e));
                 if (!rc) ev.push_back(e);
             }
         }
+        int nsamp = 0;  // slots of this batch with events, in order
         for (int q = 0; q < batch && !rc; ++q) {
+            const bool timed = phase_ms && (slots + q) % ev_every == 0;
             if (gexec)
                 rc = hip_status(hipGraphLaunch(gexec, st));
             else
                 rc = hip_status(launch_slot(table, L[0].dual_bytes, sh, st,
-                                            phase_ms ? &ev[(size_t)nev * q] : nullptr, nev));
+                                            timed ? &ev[(size_t)nev * nsamp] : nullptr, nev));
+            nsamp += timed ? 1 : 0;
         }
+        slots += batch;
+        sampled += nsamp;
         for (int c = 0; c < n && !rc; ++c)
             rc = hip_status(hipMemcpyAsync(&sc[c], (const char *)ws[c] + L[c].scalars, sizeof(DevScalars),
                                            hipMemcpyDeviceToHost, st));
         if (!rc) rc = hip_status(hipStreamSynchronize(st));
         if (!rc && phase_ms)
-            for (int q = 0; q < batch && !rc; ++q)
+            for (int q = 0; q < nsamp && !rc; ++q)
                 for (int ph = 0; ph < nph && !rc; ++ph) {
                     float ms = 0.f;
                     rc = hip_status(hipEventElapsedTime(&ms, ev[(size_t)nev * q + ph],
@@ -257,6 +267,8 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         }
         if (batch == 0 || behind <= 0) break;
     }
+    if (phase_ms && sampled > 0 && sampled < slots)
+        for (int q = 0; q < nph; ++q) phase_ms[q] *= (double)slots / (double)sampled;
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);

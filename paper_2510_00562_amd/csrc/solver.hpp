@@ -101,6 +101,7 @@ constexpr int kPointThreads = 256;
 #define GEO_SWEEP_B_BLOCKS 2048
 #endif
 constexpr int kSweepBBlocks = GEO_SWEEP_B_BLOCKS;  // grid-stride blocks of sweep B per cube
+constexpr int kTimedEvery = 8;  // geo_step_timed: events around every 8th sweep A
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
