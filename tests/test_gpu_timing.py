@@ -1,0 +1,71 @@
+"""The instrumented entry points (geo_step_profiled: events at every phase
+boundary; geo_step_timed: events around every 8th fused sweep) run the same
+launches as geo_step, so their iterates equal geo_step's bit for bit, and
+their times are positive and consistent with each other."""
+import numpy as np
+import pytest
+
+from gpu_helpers import announce, dev, f32, host, torch_cuda
+from synth.cubes import SMALL_64x64x16, like, make_cube
+
+pytestmark = pytest.mark.gpu
+
+
+def _state(geo, dims, p, vd, ws):
+    torch = torch_cuda()
+    out = {}
+    for name in ("u", "s", "t", "y4"):
+        x = torch.empty_like(vd)
+        geo.geo_state_get(dims, p, ws, name, vd, x)
+        out[name] = host(x)
+    return out
+
+
+@pytest.mark.parametrize("n_iter", [1, 7, 8, 9, 30])
+def test_instrumented_steps_equal_plain_steps(n_iter):
+    announce(f"geo_step vs geo_step_timed vs geo_step_profiled, 70x90x20, {n_iter} iterations")
+    torch_cuda()
+    import paper_2510_00562_amd as geo
+    c = make_cube(like(SMALL_64x64x16, n1=70, n2=90, n3=20, seed=5))
+    vd = dev(f32(c["v"]))
+    dims = geo.dims_of(vd.shape)
+    p = geo.params(c["eps"], c["alpha"], c["beta"], omega=c["omega"])
+    states, results = [], []
+    for how in ("plain", "timed", "profiled"):
+        ws = geo.Workspace(geo.geo_workspace_size(dims, p))
+        geo.geo_state_init(dims, p, vd, ws)
+        if how == "plain":
+            res = geo.geo_step(dims, p, vd, ws, n_iter)
+        elif how == "timed":
+            res, ms = geo.geo_step_timed(dims, p, vd, ws, n_iter)
+            assert ms > 0.0
+        else:
+            res, phase = geo.geo_step_profiled(dims, p, vd, ws, n_iter)
+            assert set(phase) == {"sweep_a", "l1_select", "sweep_b"}
+            assert all(x > 0.0 for x in phase.values())
+        assert res.iters == n_iter
+        states.append(_state(geo, dims, p, vd, ws))
+        results.append((res.r, res.tau_s, res.tau_t, res.rel_change))
+    for other in states[1:]:
+        for name, x in states[0].items():
+            assert np.array_equal(other[name], x), name
+    assert results[1] == results[0] and results[2] == results[0]
+
+
+def test_sampled_sweep_time_is_consistent():
+    """The estimate from every 8th launch agrees with the time summed over
+    every launch (same cube, same number of iterations) to within 25%."""
+    announce("geo_step_timed estimate vs geo_step_profiled sum, 256x256x64, 64 iterations")
+    torch_cuda()
+    import paper_2510_00562_amd as geo
+    c = make_cube(like(SMALL_64x64x16, n1=256, n2=256, n3=64, seed=6))
+    vd = dev(f32(c["v"]))
+    dims = geo.dims_of(vd.shape)
+    p = geo.params(c["eps"], c["alpha"], c["beta"], omega=c["omega"], tol=0.0)
+    ws = geo.Workspace(geo.geo_workspace_size(dims, p))
+    geo.geo_state_init(dims, p, vd, ws)
+    geo.geo_step(dims, p, vd, ws, 40)  # past the first full threshold searches
+    _, ms = geo.geo_step_timed(dims, p, vd, ws, 64)
+    _, phase = geo.geo_step_profiled(dims, p, vd, ws, 64)
+    print(f"sampled {ms:.3f} ms, every launch {phase['sweep_a']:.3f} ms", flush=True)
+    assert ms == pytest.approx(phase["sweep_a"], rel=0.25)
