@@ -5,7 +5,9 @@ benchmark times, and of the BF16 dual storage.
   (every state array within 1e-6 relative L2 of the FP64 oracle) and 40
   iterations from Alg. 1's initial point, long enough to leave the full radix
   search of the l1 thresholds for the warm-window search.
-- 512 x 512 x 224: three iterations from the initial point, FP32 state.
+- 512 x 512 x 224: three iterations from the initial point, FP32 state; and
+  after 300 iterations, the invariants of every iterate and one iteration
+  against the oracle started from the GPU's state.
 - BF16 storage of the duals y1..y4 (FP32 arithmetic): one iteration from a
   state whose duals are BF16 numbers matches the oracle to FP32 rounding on
   the primal arrays and to one BF16 rounding on the duals; over 200
@@ -94,6 +96,38 @@ def test_large_cube_three_iterations(ora):
     S = ora.Solver(v, prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"])
     S.step(3)
     compare(g, S.state, 1e-5)
+
+
+def test_large_cube_step_after_300_iterations(ora):
+    """At 512 x 512 x 224, after 300 iterations in the benchmark's launch
+    configuration (predicted threshold windows warm): the GPU's state obeys
+    what every iterate of Alg. 1 obeys (box, l1 radii, zero masked entries),
+    and its next iteration equals one FP64 oracle iteration from that state
+    (every array within 1e-6 relative L2, scalars within 1e-6)."""
+    c = make_cube(CUBE_512x512x224)
+    v = f32(c["v"])
+    announce(f"large cube {v.shape}: one step after 300 iterations")
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=c["omega"])
+    geo, dims, p, ws, vd = gpu_solver(v.shape, v, prm)
+    geo.geo_step(dims, p, vd, ws, 300)
+    g = get_state(geo, dims, p, ws, vd, v.shape)
+    n3, n1, n2 = v.shape
+    assert g["u"].min() >= 0.0 and g["u"].max() <= 1.0
+    assert np.abs(g["s"]).sum() <= prm["alpha"] * (1 + 1e-5)
+    assert np.abs(g["t"]).sum() <= prm["beta"] * (1 + 1e-5)
+    # dual edge fields on Neumann edges and w on the matching grids stay 0
+    assert not g["y1"][0][:, n1 - 1, :].any() and not g["y1"][1][:, :, n2 - 1].any()
+    assert not g["y2"][:, n3 - 1].any() and not g["y3"][:, n1 - 1, :].any()
+    assert not g["w1"][0:2][:, :, n1 - 1, :].any() and not g["w1"][2:4][:, :, :, n2 - 1].any()
+    S = ora.Solver(v, prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"], state=g)
+    del g
+    S.step(1)
+    res = geo.geo_step(dims, p, vd, ws, 1)
+    compare(get_state(geo, dims, p, ws, vd, v.shape), S.state, 1e-6)
+    rel, r, ts, tt = S.trace[-1]
+    assert res.r == pytest.approx(r, rel=1e-6)
+    assert res.tau_s == pytest.approx(ts, rel=1e-6)
+    assert res.tau_t == pytest.approx(tt, rel=1e-6)
 
 
 @pytest.mark.parametrize("shape", [(17, 9, 130), (33, 20, 64)])
