@@ -280,7 +280,13 @@ __global__ __launch_bounds__(kSelThreads) void k_select_level(SelState *sel, His
 // block prepares the full radix search (level 0) on the whole field.
 constexpr int kWinThreads = 1024;
 constexpr int kWinBins = 1024;
-constexpr int kCandLds = 28672;  // candidates staged in LDS (112 KB); more are read from HBM
+constexpr int kCandLds = 28672;  // candidates staged in LDS (112 KB); more are streamed
+// More candidates than kCandLds are streamed through LDS in chunks of kChunk
+// at every radix level. In the pass whose range holds at most kComp of
+// them, the ones in range are also compacted into the first kComp entries,
+// and the following levels read only those.
+constexpr int kChunk = 16384;
+constexpr int kComp = kCandLds - kChunk;
 
 // Block-wide exclusive prefix sum (kWinThreads threads, fixed order, so the
 // FP64 results are deterministic). wsum: kWinThreads/64 entries of LDS.
@@ -499,39 +505,62 @@ __device__ void level_step(SelState *sel, Hist *hist, int f)
 // Blocks past the search's read sweep B's inputs once, so that sweep B finds
 // them in the memory-side cache (the search itself keeps only two CUs per
 // cube busy). The values are consumed by an empty asm statement only.
+// Every (cube, array) pair is a segment of one flat index space of 16-byte
+// words, so a block's loads go out together whatever the number of cubes.
 __device__ void prefetch_sweep_b_inputs(const char *table, int stride, int ncubes, int pb, int np)
 {
-    // at most GEO_PREFETCH_BUDGET MB in all: the leading part of every array,
-    // which is what sweep B's first grid-stride rounds read
-    double total = 0.0;
-    for (int c = 0; c < ncubes; ++c) {
-        const CubeCommon &cc = *reinterpret_cast<const CubeCommon *>(table + (size_t)c * stride);
-        if (idle(cc.sc)) continue;
-        for (int a = 0; a < 5; ++a)
-            if ((GEO_PREFETCH_MASK >> a) & 1) total += (double)cc.bin_bytes[a];
-    }
-    const double frac = total > 0.0 ? fmin(1.0, GEO_PREFETCH_BUDGET * 1048576.0 / total) : 0.0;
-    for (int c = 0; c < ncubes; ++c) {
+    constexpr int kSeg = kMaxBatch * 5;
+    static_assert(kSeg <= kWinThreads, "one segment per thread");
+    __shared__ uint32_t seg0[kSeg + 1];  // first flat index of each segment
+    __shared__ const uint4 *segp[kSeg];
+    __shared__ uint32_t wsu[kWinThreads / 64];
+    __shared__ double wsd[3 * (kWinThreads / 64)];
+    const int tid = threadIdx.x;
+    const uint4 *p = nullptr;
+    double bytes = 0.0;
+    if (tid < 5 * ncubes) {
+        const int c = tid / 5, a = tid % 5;
         const CubeCommon &cc = *reinterpret_cast<const CubeCommon *>(table + (size_t)c * stride);
         const DevScalars *sc = cc.sc;
-        if (idle(sc)) continue;
-        const int par = (int)(sc->iter & 1u);
-        for (int a = 0; a < 5; ++a) {
-            if (!((GEO_PREFETCH_MASK >> a) & 1)) continue;
-            const uint4 *p = reinterpret_cast<const uint4 *>(cc.bin[par][a]);
-            const size_t n16 = (size_t)(frac * (double)(cc.bin_bytes[a] / 16));
-            const size_t stride16 = (size_t)np * kWinThreads;
-            for (size_t i = (size_t)pb * kWinThreads + threadIdx.x; i < n16; i += 4 * stride16) {
-                uint4 x[4];
+        if (((GEO_PREFETCH_MASK >> a) & 1) && !idle(sc)) {
+            p = reinterpret_cast<const uint4 *>(cc.bin[sc->iter & 1u][a]);
+            bytes = (double)cc.bin_bytes[a];
+        }
+    }
+    // at most GEO_PREFETCH_BUDGET MB in all: the leading part of every
+    // array, which is what sweep B's first grid-stride rounds read
+    double total = bytes, z1 = 0.0, z2 = 0.0;
+    block_sum3(total, z1, z2, wsd);
+    const double frac = total > 0.0 ? fmin(1.0, GEO_PREFETCH_BUDGET * 1048576.0 / total) : 0.0;
+    const uint32_t n16 = (uint32_t)(frac * (bytes / 16.0));
+    uint32_t all;
+    const uint32_t first = block_exclusive_scan<uint32_t>(n16, wsu, all);
+    if (tid < kSeg) {
+        seg0[tid] = first;
+        segp[tid] = p;
+    }
+    if (tid == 0) seg0[kSeg] = all;
+    __syncthreads();
+    const int nseg = 5 * ncubes;
+    const uint32_t G = (uint32_t)np * kWinThreads;
+    for (uint32_t i = (uint32_t)pb * kWinThreads + tid; i < all; i += 4 * G) {
+        uint4 x[4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const size_t k = i + u * stride16;
-                    x[u] = k < n16 ? p[k] : make_uint4(0u, 0u, 0u, 0u);
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t k = i + u * G;
+            x[u] = make_uint4(0u, 0u, 0u, 0u);
+            if (k < all) {
+                int lo = 0, hi = nseg - 1;  // last segment that starts at or before k
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (seg0[mid] <= k) lo = mid;
+                    else hi = mid - 1;
                 }
-#pragma unroll
-                for (int u = 0; u < 4; ++u) asm volatile("" ::"v"(x[u].x));
+                x[u] = segp[lo][k - seg0[lo]];
             }
         }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) asm volatile("" ::"v"(x[u].x));
     }
 }
 
@@ -571,7 +600,7 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
     __shared__ double tot[3];
     __shared__ int verdict;  // 0 searching, 1 done, 2 full search needed
     __shared__ int best;
-    __shared__ uint32_t ovf, ctot;
+    __shared__ uint32_t ovf, ctot, ncomp, nin;
     __shared__ uint32_t nbase;
     __shared__ int nshift, nnb;
     __shared__ double nS, nC;
@@ -664,11 +693,12 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         base = Pa & ~((1u << shift) - 1u);
         nb = (int)((Pb - base) >> shift) + 1;
     }
-    const int total = (int)ctot;
+    int total = (int)ctot;
     // Stage the candidates in LDS once: one wavefront per slice, each lane an
     // asynchronous global-to-LDS load into the slice's place, so all loads
     // are in flight together.
-    const bool staged = verdict == 0 && total <= kCandLds;
+    bool staged = verdict == 0 && total <= kCandLds;
+    bool compact = false;  // this level's streaming pass also compacts
     if (staged) {
         const int lane = tid & 63;
         for (int b = tid >> 6; b < grid_a; b += kWinThreads / 64) {
@@ -689,9 +719,11 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         if (tid == 0) best = -1;
         __syncthreads();
         const uint32_t lim = base + ((uint32_t)nb << shift);  // exclusive end of the range
-        // the candidates sit in per-block slices written by sweep A; a flat
-        // index maps to a slice by binary search over the prefix sums, so
-        // every thread issues independent loads
+        auto add = [&](uint32_t p) {
+            const uint32_t b = (p - base) >> shift;
+            atomicAdd(&cnt[b], 1u);
+            atomicAdd(&ms[b], (unsigned long long)significand(p));
+        };
         if (staged) {
             // four candidates per step, so their LDS reads overlap
             for (int q0 = tid; q0 < total; q0 += 4 * kWinThreads) {
@@ -704,29 +736,51 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const uint32_t p = pq[u];
-                    if (q0 + u * kWinThreads < total && p >= base && p < lim) {
-                        const uint32_t b = (p - base) >> shift;
-                        atomicAdd(&cnt[b], 1u);
-                        atomicAdd(&ms[b], (unsigned long long)significand(p));
+                    if (q0 + u * kWinThreads < total && p >= base && p < lim) add(p);
+                }
+            }
+        } else {
+            // stream the tile slices through LDS, kChunk candidates at a time
+            // (flat index order of the prefix sums): a wavefront copies the
+            // part of a slice that falls in the chunk with asynchronous
+            // global-to-LDS loads, then every thread bins the chunk
+            if (tid == 0) ncomp = 0u;
+            float *chunk = cl + kComp;
+            const int lane = tid & 63;
+            for (int c0 = 0; c0 < total; c0 += kChunk) {
+                const int c1 = c0 + kChunk < total ? c0 + kChunk : total;
+                __syncthreads();  // the previous chunk has been binned
+                for (int b = tid >> 6; b < grid_a; b += kWinThreads / 64) {
+                    const int p0 = (int)pre[b], p1 = b + 1 < grid_a ? (int)pre[b + 1] : total;
+                    const int a = p0 > c0 ? p0 : c0, e = p1 < c1 ? p1 : c1;
+                    const float *src = cand + ((int64_t)f * grid_a + b) * capb;
+                    for (int o = a; o < e; o += 64)
+                        if (o + lane < e)
+                            __builtin_amdgcn_global_load_lds(src + (o - p0) + lane, chunk + (o - c0), 4, 0,
+                                                             0);
+                }
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+                const int nc = c1 - c0;
+                for (int q0 = tid; q0 < nc; q0 += 4 * kWinThreads) {
+                    uint32_t pq[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int q = q0 + u * kWinThreads;
+                        pq[u] = q < nc ? __float_as_uint(chunk[q]) : 0u;
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const uint32_t p = pq[u];
+                        if (q0 + u * kWinThreads < nc && p >= base && p < lim) {
+                            add(p);
+                            if (compact) {
+                                const uint32_t k = atomicAdd(&ncomp, 1u);
+                                if (k < (uint32_t)kComp) cl[k] = __uint_as_float(p);
+                            }
+                        }
                     }
                 }
-            }
-        }
-        for (int q = staged ? total : tid; q < total; q += kWinThreads) {
-            uint32_t p;
-            {
-                int lo = 0, hi = grid_a - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (pre[mid] <= (uint32_t)q) lo = mid;
-                    else hi = mid - 1;
-                }
-                p = __float_as_uint(cand[((int64_t)f * grid_a + lo) * capb + (q - (int)pre[lo])]);
-            }
-            if (p >= base && p < lim) {
-                const uint32_t b = (p - base) >> shift;
-                atomicAdd(&cnt[b], 1u);
-                atomicAdd(&ms[b], (unsigned long long)significand(p));
             }
         }
         __syncthreads();
@@ -775,17 +829,24 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
                         nnb = 1 << (shift - ns);
                         nS = Sb;
                         nC = Cb;
+                        nin = cnt[b];  // candidates in the next level's range
                     }
                 }
             }
         }
         __syncthreads();
+        if (compact) {  // the pass above left the level's range in cl[0, ncomp)
+            staged = true;
+            compact = false;
+            total = (int)ncomp;
+        }
         if (verdict == 0) {
             base = nbase;
             shift = nshift;
             nb = nnb;
             Sab = nS;
             Cab = nC;
+            compact = !staged && nin <= (uint32_t)kComp;
         }
         __syncthreads();
     }
