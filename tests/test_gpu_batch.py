@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from gpu_helpers import announce, dev, f32, rel_l2, torch_cuda
-from synth.cubes import SMALL_64x64x16, like, make_cube
+from synth.cubes import CUBE_512x512x224, SMALL_64x64x16, like, make_cube
 from test_gpu_step import STATE, get_state
 
 pytestmark = pytest.mark.gpu
@@ -123,3 +123,24 @@ def test_batched_cube_matches_oracle(ora):
         S = ora.Solver(c["v"], c["eps"], c["alpha"], c["beta"], omega=0.03)
         S.step(60)
         assert rel_l2(s["u"], S.u) <= 1e-5
+
+
+def test_band_chunk_raised_at_the_tile_limit():
+    """512 x 512 x 224 with 8-band tiles would need 7168 tiles, beyond the
+    4096 a launch supports: the library doubles the chunk to 16 bands, so the
+    request for 8 and the request for 16 run the same tiles and give the same
+    bits; 32-band tiles differ only by FP64 summation order."""
+    announce("band chunk 8 on 512x512x224: raised to 16")
+    torch = torch_cuda()
+    import paper_2510_00562_amd as geo
+    c = make_cube(CUBE_512x512x224)
+    out = {}
+    for kc in (8, 16, 32):
+        d, p, vd, ws = setup(geo, c, band_chunk=kc)
+        geo.geo_step(d, p, vd, ws, 3)
+        u = torch.empty_like(vd)
+        geo.geo_state_get(d, p, ws, "u", vd, u)
+        out[kc] = u.cpu().numpy()
+        del ws
+    assert np.array_equal(out[8], out[16])
+    assert rel_l2(out[32], out[16]) <= 1e-6

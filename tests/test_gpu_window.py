@@ -5,7 +5,9 @@ more values than fit in LDS at once.
 Cubes of the uneven batch whose s-field threshold sinks toward 0 put
 hundreds of thousands of |z| values inside the window in some iterations.
 The search then streams them through LDS in chunks and compacts the
-candidates of a deeper radix level. Every iteration's thresholds must still
+candidates of a deeper radix level. In one of them the window overflows the
+candidate slots of the tiles, which sends those iterations to the full
+radix search. Every iteration's thresholds must still
 equal the FP64 oracle's, and the iterates must follow it."""
 import numpy as np
 import pytest
@@ -27,13 +29,18 @@ def test_window_search_beyond_lds(ora, which):
     announce(f"window search beyond LDS: batch cube {which} {v.shape}, {iters} iterations")
     prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=c["omega"])
     geo, dims, p, ws, vd = gpu_solver(v.shape, v, prm)
-    taus, cands = [], []
+    taus, cands, fallbacks = [], [], 0
     for _ in range(iters):
         res = geo.geo_step(dims, p, vd, ws, 1)
         taus.append((res.tau_s, res.tau_t))
         cands.append(max(res.cand_s, res.cand_t))
-    print("candidates per iteration:", cands, flush=True)
+        fallbacks += res.fallback_passes
+    print("candidates per iteration:", cands, "full searches:", fallbacks, flush=True)
     assert max(cands) > CAND_LDS  # the streamed search ran
+    if which == 28:
+        # tiles ran out of candidate slots (N/16 in all): the search fell
+        # back to the full radix search over the cube in those iterations
+        assert max(cands) >= (v.size // 16) * 0.99 and fallbacks > 2
     g = get_state(geo, dims, p, ws, vd, v.shape)
     S = ora.Solver(v, prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"])
     S.step(iters)
