@@ -315,8 +315,10 @@ __device__ __forceinline__ T block_exclusive_scan(T x, T *wsum, T &total)
 
 // Two block-wide exclusive prefix sums at once (the shuffles of the two
 // chains interleave). wsum: 2 * kWinThreads/64 entries of LDS.
+// trailing = false leaves out the closing barrier: the caller passes a
+// barrier of its own before wsum is written again.
 __device__ __forceinline__ void block_exclusive_scan2(double &a, double &b, double *wsum,
-                                                      double &ta, double &tb)
+                                                      double &ta, double &tb, bool trailing = true)
 {
     constexpr int NW = kWinThreads / 64;
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -345,7 +347,7 @@ __device__ __forceinline__ void block_exclusive_scan2(double &a, double &b, doub
         sa += va;
         sb += vb;
     }
-    __syncthreads();
+    if (trailing) __syncthreads();
     ta = sa;
     tb = sb;
     a = ba + ia - a;
@@ -573,17 +575,12 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
                                 (int)gridDim.x - 2 * ncubes);
         return;
     }
-    const CubeCommon &cc = *reinterpret_cast<const CubeCommon *>(table + (size_t)(blockIdx.x >> 1) * stride);
+    // the launch table through the constant address space (scalar loads)
+    const4<CubeCommon> &cc = *(const4<CubeCommon> *)(table + (size_t)(blockIdx.x >> 1) * stride);
     const int f = blockIdx.x & 1;
     DevScalars *sc = cc.sc;
-    if (idle(sc)) return;
     SelState *sel = sc->sel;
     Hist *hist = cc.hist;
-    if (sc->hist_slot) {  // sweep A histogrammed a radix level of a running search
-        if (sel[f].done) return;
-        level_step(sel, hist, f);
-        return;
-    }
     const double *winpart = cc.winpart;
     const int grid_a = cc.ntiles;  // candidate slices: one per tile
     const float *cand = cc.cand;
@@ -605,8 +602,15 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
     __shared__ int nshift, nnb;
     __shared__ double nS, nC;
     const int tid = threadIdx.x;
-    // the tile partials and candidate counts of sweep A (fixed order) do not
-    // depend on the search state: their loads go out together with it
+    // Every first read goes out at once: the cube's flags, the field's search
+    // state (a word per thread) and sweep A's tile partials and candidate
+    // counts (fixed order). A cube that turns out idle, or that is in a
+    // radix pass of the full search, has read a few KB for nothing.
+    const bool is_idle = idle(sc);
+    const uint32_t in_hist_slot = sc->hist_slot;
+    constexpr int kSelWords = sizeof(SelState) / 4;
+    static_assert(sizeof(SelState) % 4 == 0 && kSelWords <= kWinThreads, "search state by words");
+    const uint32_t sel_word = tid < kSelWords ? reinterpret_cast<const uint32_t *>(&sel[f])[tid] : 0u;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
     uint32_t mine = 0u, cbs[kMaxTiles / kWinThreads];  // this thread's consecutive slices
     bool my_ovf = false;
@@ -631,8 +635,14 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         cbs[q] = cb;
         mine += cb;
     }
+    if (is_idle) return;
+    if (in_hist_slot) {  // sweep A histogrammed a radix level of a running search
+        if (sel[f].done) return;
+        level_step(sel, hist, f);
+        return;
+    }
+    if (tid < kSelWords) reinterpret_cast<uint32_t *>(&s)[tid] = sel_word;
     if (tid == 0) {
-        s = sel[f];
         ovf = 0u;
         verdict = 0;
     }
@@ -709,15 +719,15 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         }
         __builtin_amdgcn_s_waitcnt(0);
     }
+    // bins start empty; each level empties its bins again as it reads them
+    for (int b = tid; b < kWinBins; b += kWinThreads) {
+        cnt[b] = 0u;
+        ms[b] = 0ull;
+    }
+    if (tid == 0) best = -1;
     __syncthreads();
-    // radix levels over the candidates
+    // radix levels over the candidates: four barriers each
     for (int level = 0; level < 5 && verdict == 0; ++level) {
-        for (int b = tid; b < kWinBins; b += kWinThreads) {
-            cnt[b] = 0u;
-            ms[b] = 0ull;
-        }
-        if (tid == 0) best = -1;
-        __syncthreads();
         const uint32_t lim = base + ((uint32_t)nb << shift);  // exclusive end of the range
         auto add = [&](uint32_t p) {
             const uint32_t b = (p - base) >> shift;
@@ -788,10 +798,14 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         // scan (a prefix scan in reversed bin order)
         const int b = kWinBins - 1 - tid;  // reversed
         const bool valid = b < nb;
-        const double bs = valid ? bin_value(ms[b], base + ((uint32_t)b << shift)) : 0.0;
-        const double bc = valid ? (double)cnt[b] : 0.0;
+        const unsigned long long mb = ms[b];
+        const uint32_t cb = cnt[b];
+        cnt[b] = 0u;  // only this thread reads bin b: empty it for the next level
+        ms[b] = 0ull;
+        const double bs = valid ? bin_value(mb, base + ((uint32_t)b << shift)) : 0.0;
+        const double bc = valid ? (double)cb : 0.0;
         double allS, allC, xS = bs, xC = bc;
-        block_exclusive_scan2(xS, xC, wsd, allS, allC);
+        block_exclusive_scan2(xS, xC, wsd, allS, allC, false);
         const double aboveS = Sab + xS;
         const double aboveC = Cab + xC;
         const double radius = s.radius;
@@ -829,12 +843,13 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
                         nnb = 1 << (shift - ns);
                         nS = Sb;
                         nC = Cb;
-                        nin = cnt[b];  // candidates in the next level's range
+                        nin = cb;  // candidates in the next level's range
                     }
                 }
             }
         }
         __syncthreads();
+        if (tid == 0) best = -1;  // every thread has read it
         if (compact) {  // the pass above left the level's range in cl[0, ncomp)
             staged = true;
             compact = false;
@@ -848,7 +863,6 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
             Cab = nC;
             compact = !staged && nin <= (uint32_t)kComp;
         }
-        __syncthreads();
     }
     if (tid == 0) {
         SelState o = s;
