@@ -113,6 +113,10 @@ __device__ __forceinline__ void st2_nt(bf16x2 *p, float2 x)
 #endif
 }
 
+// One component (c = 0 first, 1 second) of a stored pair, nontemporal.
+__device__ __forceinline__ void st_comp_nt(float2 *p, int c, float x) { st_nt(reinterpret_cast<float *>(p) + c, x); }
+__device__ __forceinline__ void st_comp_nt(bf16x2 *p, int c, float x) { st_nt(reinterpret_cast<bf16 *>(p) + c, x); }
+
 // Loads of values no other thread or tile reads (no halo reuse).
 #ifndef GEO_NT_LOADS
 #define GEO_NT_LOADS 1

@@ -473,18 +473,18 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
                                        + 0.5f * (W[2][c1] + W[2][c1 + W1]));
                 const float ph = mh * (wk[f][1] + 0.25f * ((W[0][c1] + W[0][c1 + 1]) + (W[0][c1 - W1] + W[0][c1 - W1 + 1]))
                                        + 0.5f * (W[3][c1] + W[3][c1 + 1]));
-                const P *ys = f ? src.y2 : src.y1;
                 P *yd = f ? dst.y2 : dst.y1;
-                float2 y = make_float2(sY[buf][2 * f][c2], sY[buf][2 * f + 1][c2]);
-                // masked entries (last row / column) keep their stored value
-                if (oi > n1 - 2 || oj > n2 - 2) {
-                    const float2 raw = ld2(ys + q);
-                    if (oi > n1 - 2) y.x = raw.x;
-                    if (oj > n2 - 2) y.y = raw.y;
-                }
+                const float2 y = make_float2(sY[buf][2 * f][c2], sY[buf][2 * f + 1][c2]);
                 const float gv = f ? msk * (dn_v - du_v) : du_v;
                 const float gh = f ? msk * (dn_h - du_h) : du_h;
-                st2_nt(yd + q, make_float2(y.x + kStepY * (gv - pv), y.y + kStepY * (gh - ph)));
+                const float2 yn = make_float2(y.x + kStepY * (gv - pv), y.y + kStepY * (gh - ph));
+                // A masked entry (vertical component on the last row,
+                // horizontal on the last column) keeps its value, and both
+                // sides hold the same one: it is not written at all.
+                const bool mx = oi > n1 - 2, my = oj > n2 - 2;
+                if (!mx && !my) st2_nt(yd + q, yn);
+                else if (!mx) st_comp_nt(yd + q, 0, yn.x);
+                else if (!my) st_comp_nt(yd + q, 1, yn.y);
             }
         };
 
@@ -750,8 +750,9 @@ __global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
 }
 
 template <typename DT>
-__global__ __launch_bounds__(NPT) void k_init(Dims d, const float *v, Side<DT> s0, DevScalars *sc,
-                                              double eps, double tol, double alpha, double beta)
+__global__ __launch_bounds__(NPT) void k_init(Dims d, const float *v, Side<DT> s0, Side<DT> s1,
+                                              DevScalars *sc, double eps, double tol, double alpha,
+                                              double beta)
 {
     using P = typename PairOf<DT>::type;
     const int64_t N = d.plane;
@@ -766,8 +767,11 @@ __global__ __launch_bounds__(NPT) void k_init(Dims d, const float *v, Side<DT> s
             s0.w1[g * N + q] = z2;
             s0.w2[g * N + q] = z2;
         }
+        // y1, y2 on both sides: their masked entries are never rewritten
         st2((P *)s0.y1 + q, z2);
         st2((P *)s0.y2 + q, z2);
+        st2((P *)s1.y1 + q, z2);
+        st2((P *)s1.y2 + q, z2);
         st(s0.y3 + q, 0.f);
         st(s0.y4 + q, 0.f);
     }
@@ -849,7 +853,12 @@ __global__ __launch_bounds__(NPT) void k_state_io(Dims d, Side<DT> s0, Side<DT> 
                 break;
             case GEO_VAR_Y1:
             case GEO_VAR_Y2:
-                if (pl == 0) st2(yp + q, make_float2(in[q], in[q + N]));
+                // both sides: sweep A never rewrites the masked entries
+                if (pl == 0) {
+                    const float2 y = make_float2(in[q], in[q + N]);
+                    st2((var == GEO_VAR_Y1 ? s0.y1 : s0.y2) + q, y);
+                    st2((var == GEO_VAR_Y1 ? s1.y1 : s1.y2) + q, y);
+                }
                 break;
             case GEO_VAR_Y3: st(s.y3 + q, in[q]); break;
             default: st(s.y4 + q, in[q]); break;
@@ -1016,10 +1025,11 @@ hipError_t launch_init(const Dims &d, const float *v, void *ws, const Layout &L,
     DevScalars *sc = (DevScalars *)((char *)ws + L.scalars);
     if (L.dual_bytes == 2)
         hipLaunchKernelGGL(k_init<bf16>, dim3(grid_for(d.plane)), dim3(NPT), 0, st, d, v,
-                           side_of<bf16>(ws, L, 0), sc, eps, tol, alpha, beta);
+                           side_of<bf16>(ws, L, 0), side_of<bf16>(ws, L, 1), sc, eps, tol, alpha, beta);
     else
         hipLaunchKernelGGL(k_init<float>, dim3(grid_for(d.plane)), dim3(NPT), 0, st, d, v,
-                           side_of<float>(ws, L, 0), sc, eps, tol, alpha, beta);
+                           side_of<float>(ws, L, 0), side_of<float>(ws, L, 1), sc, eps, tol, alpha,
+                           beta);
     return hipGetLastError();
 }
 
