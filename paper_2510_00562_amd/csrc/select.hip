@@ -499,7 +499,7 @@ __device__ void level_step(SelState *sel, Hist *hist, int f)
 }
 
 #ifndef GEO_PREFETCH_BUDGET
-#define GEO_PREFETCH_BUDGET 128  // MB: half the memory-side cache
+#define GEO_PREFETCH_BUDGET 96  // MB, of the 256 MB memory-side cache
 #endif
 #ifndef GEO_PREFETCH_MASK
 #define GEO_PREFETCH_MASK 31  // s, t, y3, y4, the y4 intermediate
