@@ -717,22 +717,40 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh
 // One block per cube of the table (entries of `stride` bytes).
 __global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
 {
-    const CubeCommon &cc = *reinterpret_cast<const CubeCommon *>(table + (size_t)blockIdx.x * stride);
+    // the launch table through the constant address space (scalar loads)
+    const4<CubeCommon> &cc = *(const4<CubeCommon> *)(table + (size_t)blockIdx.x * stride);
     DevScalars *sc = cc.sc;
-    if (idle(sc) || !(sc->sel[0].done && sc->sel[1].done)) return;
     const double *part = cc.part;
     const int grid_a = cc.ntiles, blocks_b = cc.nb;
-    __shared__ double red[NPT / 64];
+    __shared__ double red[3 * (NPT / 64)];
+    // the partials are read together with the flags that may make them moot
+    const bool skip = idle(sc) || !(sc->sel[0].done && sc->sel[1].done);
     double du2 = 0.0, u2 = 0.0, r2 = 0.0;
     for (int b = threadIdx.x; b < grid_a; b += NPT) {
         du2 += part[2 * b];
         u2 += part[2 * b + 1];
     }
     for (int b = threadIdx.x; b < blocks_b; b += NPT) r2 += part[2 * grid_a + b];
-    du2 = block_sum<NPT>(du2, red);
-    u2 = block_sum<NPT>(u2, red);
-    r2 = block_sum<NPT>(r2, red);
+    if (skip) return;
+    // the three block sums at once, in the order of block_sum: a butterfly
+    // within each wavefront, then the wavefronts in order (thread 0)
+    du2 = wave_sum(du2);
+    u2 = wave_sum(u2);
+    r2 = wave_sum(r2);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[wid] = du2;
+        red[NPT / 64 + wid] = u2;
+        red[2 * (NPT / 64) + wid] = r2;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
+        du2 = u2 = r2 = 0.0;
+        for (int w = 0; w < NPT / 64; ++w) {
+            du2 += red[w];
+            u2 += red[NPT / 64 + w];
+            r2 += red[2 * (NPT / 64) + w];
+        }
         const double r = sqrt(r2);
         const double rel = u2 > 0.0 ? sqrt(du2) / sqrt(u2) : __longlong_as_double(0x7ff0000000000000ll);
         const bool bad = !isfinite(du2) || !isfinite(u2) || !isfinite(r2);
