@@ -704,6 +704,28 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         nb = (int)((Pb - base) >> shift) + 1;
     }
     int total = (int)ctot;
+    // Candidates beyond the LDS capacity are streamed through it in chunks.
+    // For a chunk [c0, c1) of the flat order (the slices of the tiles one
+    // after another, slice b starting at pre[b]), each thread copies the
+    // part of its own slices (those of its `per` consecutive tiles) that
+    // falls in the chunk to dst[position - c0], four loads at a time so that
+    // they are in flight together: no wavefront walks the slice list once
+    // per chunk.
+    auto copy_own = [&](int c0, int c1, float *dst) {
+        for (int b = per * tid; b < per * tid + per && b < grid_a; ++b) {
+            const int p0 = (int)pre[b], p1 = b + 1 < grid_a ? (int)pre[b + 1] : total;
+            const int lo = p0 > c0 ? p0 : c0, hi = p1 < c1 ? p1 : c1;
+            const float *src = cand + ((int64_t)f * grid_a + b) * capb;
+            for (int i0 = lo; i0 < hi; i0 += 4) {
+                float x[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) x[u] = i0 + u < hi ? src[i0 + u - p0] : 0.f;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (i0 + u < hi) dst[i0 + u - c0] = x[u];
+            }
+        }
+    };
     // Stage the candidates in LDS once: one wavefront per slice, each lane an
     // asynchronous global-to-LDS load into the slice's place, so all loads
     // are in flight together.
@@ -750,26 +772,14 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
                 }
             }
         } else {
-            // stream the tile slices through LDS, kChunk candidates at a time
-            // (flat index order of the prefix sums): a wavefront copies the
-            // part of a slice that falls in the chunk with asynchronous
-            // global-to-LDS loads, then every thread bins the chunk
+            // stream the candidates through LDS, kChunk at a time in flat
+            // order, then every thread bins the chunk
             if (tid == 0) ncomp = 0u;
             float *chunk = cl + kComp;
-            const int lane = tid & 63;
             for (int c0 = 0; c0 < total; c0 += kChunk) {
                 const int c1 = c0 + kChunk < total ? c0 + kChunk : total;
                 __syncthreads();  // the previous chunk has been binned
-                for (int b = tid >> 6; b < grid_a; b += kWinThreads / 64) {
-                    const int p0 = (int)pre[b], p1 = b + 1 < grid_a ? (int)pre[b + 1] : total;
-                    const int a = p0 > c0 ? p0 : c0, e = p1 < c1 ? p1 : c1;
-                    const float *src = cand + ((int64_t)f * grid_a + b) * capb;
-                    for (int o = a; o < e; o += 64)
-                        if (o + lane < e)
-                            __builtin_amdgcn_global_load_lds(src + (o - p0) + lane, chunk + (o - c0), 4, 0,
-                                                             0);
-                }
-                __builtin_amdgcn_s_waitcnt(0);
+                copy_own(c0, c1, chunk);
                 __syncthreads();
                 const int nc = c1 - c0;
                 for (int q0 = tid; q0 < nc; q0 += 4 * kWinThreads) {
