@@ -728,10 +728,14 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
     };
     // Stage the candidates in LDS once: one wavefront per slice, each lane an
     // asynchronous global-to-LDS load into the slice's place, so all loads
-    // are in flight together.
+    // are in flight together. With many small slices (more than 512 tiles)
+    // the walk over the slices costs more than the loads, and each thread
+    // copies its own slices instead.
     bool staged = verdict == 0 && total <= kCandLds;
     bool compact = false;  // this level's streaming pass also compacts
-    if (staged) {
+    if (staged && grid_a > 512) {
+        copy_own(0, total, cl);
+    } else if (staged) {
         const int lane = tid & 63;
         for (int b = tid >> 6; b < grid_a; b += kWinThreads / 64) {
             const uint32_t p0 = pre[b], p1 = b + 1 < grid_a ? pre[b + 1] : (uint32_t)total;
