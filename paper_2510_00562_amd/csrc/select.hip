@@ -598,6 +598,7 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
     __shared__ int verdict;  // 0 searching, 1 done, 2 full search needed
     __shared__ int best;
     __shared__ uint32_t ovf, ctot, ncomp, nin;
+    __shared__ uint32_t maxown;  // most candidates owned by one thread
     __shared__ uint32_t nbase;
     __shared__ int nshift, nnb;
     __shared__ double nS, nC;
@@ -644,10 +645,17 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
     if (tid < kSelWords) reinterpret_cast<uint32_t *>(&s)[tid] = sel_word;
     if (tid == 0) {
         ovf = 0u;
+        maxown = 0u;
         verdict = 0;
     }
     __syncthreads();
     if (my_ovf) atomicOr(&ovf, 1u);  // read after the scans' barriers
+    {
+        uint32_t mx = mine;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+        if ((tid & 63) == 0) atomicMax(&maxown, mx);  // read after the scans' barriers too
+    }
     if (s.radius <= 0.0) {  // zero radius: the ball is {0}
         if (tid == 0) {
             SelState o = s;
@@ -704,13 +712,11 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         nb = (int)((Pb - base) >> shift) + 1;
     }
     int total = (int)ctot;
-    // Candidates beyond the LDS capacity are streamed through it in chunks.
-    // For a chunk [c0, c1) of the flat order (the slices of the tiles one
-    // after another, slice b starting at pre[b]), each thread copies the
-    // part of its own slices (those of its `per` consecutive tiles) that
-    // falls in the chunk to dst[position - c0], four loads at a time so that
-    // they are in flight together: no wavefront walks the slice list once
-    // per chunk.
+    // Copy of the candidates at flat positions [c0, c1) (the slices of the
+    // tiles one after another, slice b starting at pre[b]) to
+    // dst[position - c0]: each thread copies the part of its own slices
+    // (those of its `per` consecutive tiles), four loads at a time so that
+    // they are in flight together.
     auto copy_own = [&](int c0, int c1, float *dst) {
         for (int b = per * tid; b < per * tid + per && b < grid_a; ++b) {
             const int p0 = (int)pre[b], p1 = b + 1 < grid_a ? (int)pre[b + 1] : total;
@@ -728,12 +734,15 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
     };
     // Stage the candidates in LDS once: one wavefront per slice, each lane an
     // asynchronous global-to-LDS load into the slice's place, so all loads
-    // are in flight together. With many small slices (more than 512 tiles)
-    // the walk over the slices costs more than the loads, and each thread
-    // copies its own slices instead.
+    // are in flight together. With many small slices (more than 512 tiles,
+    // at most 256 candidates per thread) the walk over the slices costs more
+    // than the loads, and each thread copies its own slices instead; with
+    // large slices that would leave a few threads copying thousands of
+    // values one group after another.
+    const bool own = grid_a > 512 && maxown <= 256u;
     bool staged = verdict == 0 && total <= kCandLds;
     bool compact = false;  // this level's streaming pass also compacts
-    if (staged && grid_a > 512) {
+    if (staged && own) {
         copy_own(0, total, cl);
     } else if (staged) {
         const int lane = tid & 63;
@@ -783,7 +792,21 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
             for (int c0 = 0; c0 < total; c0 += kChunk) {
                 const int c1 = c0 + kChunk < total ? c0 + kChunk : total;
                 __syncthreads();  // the previous chunk has been binned
-                copy_own(c0, c1, chunk);
+                if (own) {
+                    copy_own(c0, c1, chunk);
+                } else {
+                    const int lane = tid & 63;
+                    for (int b = tid >> 6; b < grid_a; b += kWinThreads / 64) {
+                        const int p0 = (int)pre[b], p1 = b + 1 < grid_a ? (int)pre[b + 1] : total;
+                        const int a = p0 > c0 ? p0 : c0, e = p1 < c1 ? p1 : c1;
+                        const float *src = cand + ((int64_t)f * grid_a + b) * capb;
+                        for (int o = a; o < e; o += 64)
+                            if (o + lane < e)
+                                __builtin_amdgcn_global_load_lds(src + (o - p0) + lane, chunk + (o - c0),
+                                                                 4, 0, 0);
+                    }
+                    __builtin_amdgcn_s_waitcnt(0);
+                }
                 __syncthreads();
                 const int nc = c1 - c0;
                 for (int q0 = tid; q0 < nc; q0 += 4 * kWinThreads) {
