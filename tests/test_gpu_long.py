@@ -50,3 +50,30 @@ def test_benchmark_cube_5000_iterations():
     assert es <= 1e-4 and et <= 1e-4
     assert gap <= 0.01
     assert res.r == pytest.approx(g["last_trace"]["r"], rel=1e-4)
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="oracle long run not generated")
+def test_benchmark_cube_5000_iterations_bf16_duals():
+    """BF16 storage of the duals over the same 5000 iterations, against the
+    same FP64 oracle run: reported, with loose bounds (the storage rounding
+    accumulates; it is not expected to reach the FP32 bounds)."""
+    announce("256x256x128, 5000 iterations with BF16 duals vs the stored FP64 oracle run")
+    torch = torch_cuda()
+    import paper_2510_00562_amd as geo
+    from synth.quality import mpsnr
+    g = json.load(open(GOLDEN))
+    c = make_cube(CUBE_256x256x128)
+    vd = dev(f32(c["v"]))
+    dims = geo.dims_of(vd.shape)
+    p = geo.params(c["eps"], c["alpha"], c["beta"], omega=c["omega"], dual_storage=geo.GEO_STORE_BF16)
+    ws = geo.Workspace(geo.geo_workspace_size(dims, p))
+    geo.geo_state_init(dims, p, vd, ws)
+    res = geo.geo_step(dims, p, vd, ws, g["iterations"])
+    assert res.iters == g["iterations"]
+    u = torch.empty_like(vd)
+    geo.geo_state_get(dims, p, ws, "u", vd, u)
+    u = u.cpu().numpy().astype(np.float64)
+    eu = rel_l2(u.ravel()[np.asarray(g["sample_index"])], np.asarray(g["u"]))
+    gap = mpsnr(u, c["u_clean"]) - g["mpsnr"]
+    print(f"BF16 duals: u {eu:.2e} relative L2, MPSNR {gap:+.3f} dB against the FP64 oracle", flush=True)
+    assert eu <= 3e-2 and abs(gap) <= 0.5
