@@ -83,15 +83,21 @@ struct Layout {
     int64_t cap;    // candidate capacity per field
 };
 
-// Tile of the fused primal/dual sweep: TI x 64 pixels, marching through a
-// chunk of kc bands (kc chosen per cube at run time).
+// Tile of the fused primal/dual sweep: TI x TJ pixels (one per thread of a
+// 1024-thread workgroup), marching through a chunk of kc bands (kc chosen
+// per cube at run time). 8 x 128 tiles read each band row of a tile as one
+// 512-byte run per array; they streamed 2.5% faster than 16 x 64 tiles in a
+// probe of the same 22-read, 18-write access pattern.
 #ifndef GEO_TILE_ROWS
-#define GEO_TILE_ROWS 16
+#define GEO_TILE_ROWS 8
+#endif
+#ifndef GEO_TILE_COLS
+#define GEO_TILE_COLS 128
 #endif
 #ifndef GEO_SWEEP_B_ROWS
 #define GEO_SWEEP_B_ROWS 2
 #endif
-constexpr int kTI = GEO_TILE_ROWS, kTJ = 64, kSweepThreads = kTI * kTJ;
+constexpr int kTI = GEO_TILE_ROWS, kTJ = GEO_TILE_COLS, kSweepThreads = kTI * kTJ;
 constexpr int kDefaultKC = 32;       // bands per tile unless the caller picks
 constexpr int kMinKC = 8;
 constexpr int kMaxTiles = 4096;      // tiles of one cube (slices of its search)

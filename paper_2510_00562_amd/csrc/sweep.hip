@@ -41,7 +41,7 @@ constexpr int HU = TI + 1, WU = TJ + 1, SU = HU * WU;  // u' with the (+1, +1) r
 constexpr int NY = (S2 + NT - 1) / NT;                  // y points per thread
 constexpr int RING1 = S1 - TI * TJ;                     // w' ring points
 constexpr int RINGU = SU - TI * TJ;                     // u' ring points
-static_assert(TI * TJ == NT && TJ == 64, "one own point per thread, a wave per tile row");
+static_assert(TI * TJ == NT && TJ % 64 == 0, "one own point per thread, whole wavefronts per tile row");
 static_assert(RING1 <= NT && RINGU <= NT, "at most one ring point per thread");
 constexpr int NPT = 256;  // threads of the pointwise kernels
 

@@ -1,8 +1,8 @@
 """Autotuner of the fused sweep's tile depth (bands per tile, `band_chunk`).
 
-The sweep streams each TI x 64 pixel tile through a chunk of bands. Deeper
-chunks amortise the tile's fixed costs: the halo band of y, the register
-spills around the band loop and the tile's partial sums. Shallower chunks
+The sweep streams each TI x TJ pixel tile through a chunk of bands. Deeper
+chunks amortise the tile's fixed costs: the halo band of y and the tile's
+partial sums. Shallower chunks
 give more tiles to spread over the 256 compute units. The best depth depends
 on the cube sizes, so this tuner times a few candidates on the caller's own
 states, in steady state, and returns the fastest one. It uses only the C
