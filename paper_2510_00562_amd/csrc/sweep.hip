@@ -929,8 +929,8 @@ int grid_for(int64_t n)
 template <typename DT>
 int resident_grid()
 {
-    static int cached = 0;
-    if (cached == 0) {
+    // computed once per process (thread-safe initialisation of a local static)
+    static const int cached = [] {
         int dev = 0, cus = 256, per = 2;
         if (hipGetDevice(&dev) == hipSuccess) {
             hipDeviceProp_t prop;
@@ -938,8 +938,8 @@ int resident_grid()
         }
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_a<DT>, NT, 0) != hipSuccess || per < 1)
             per = 1;
-        cached = cus * per;
-    }
+        return cus * per;
+    }();
     return cached;
 }
 
