@@ -745,12 +745,23 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
     if (staged && own) {
         copy_own(0, total, cl);
     } else if (staged) {
-        const int lane = tid & 63;
-        for (int b = tid >> 6; b < grid_a; b += kWinThreads / 64) {
-            const uint32_t p0 = pre[b], p1 = b + 1 < grid_a ? pre[b + 1] : (uint32_t)total;
-            const float *src = cand + ((int64_t)f * grid_a + b) * capb;
-            for (uint32_t o = 0; o < p1 - p0; o += 64)
-                if (o + lane < p1 - p0) __builtin_amdgcn_global_load_lds(src + o + lane, cl + p0 + o, 4, 0, 0);
+        // wavefront w takes slices w, w + 16, ...; each round of 64 of them
+        // reads their bounds with one LDS load per lane and walks them with
+        // the bounds read from the lanes (no LDS latency per slice)
+        const int w = tid >> 6, lane = tid & 63;
+        constexpr int NW = kWinThreads / 64;
+        for (int b0 = w; b0 < grid_a; b0 += NW * 64) {
+            const int bl = b0 + NW * lane;
+            const int mp0 = bl < grid_a ? (int)pre[bl] : total;
+            const int mp1 = bl + 1 < grid_a ? (int)pre[bl + 1] : total;
+            const int nsl = (grid_a - b0 + NW - 1) / NW < 64 ? (grid_a - b0 + NW - 1) / NW : 64;
+            for (int l = 0; l < nsl; ++l) {
+                const int b = b0 + NW * l;
+                const int p0 = __builtin_amdgcn_readlane(mp0, l), p1 = __builtin_amdgcn_readlane(mp1, l);
+                const float *src = cand + ((int64_t)f * grid_a + b) * capb;
+                for (int o = 0; o < p1 - p0; o += 64)
+                    if (o + lane < p1 - p0) __builtin_amdgcn_global_load_lds(src + o + lane, cl + p0 + o, 4, 0, 0);
+            }
         }
         __builtin_amdgcn_s_waitcnt(0);
     }
