@@ -200,7 +200,10 @@ __global__ __launch_bounds__(kSelThreads) void k_select_level(SelState *sel, His
                 break;
             }
         }
-        if (mine >= 0) atomicMax(&best, mine);
+        int wm = mine;  // one atomic per wavefront
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) wm = max(wm, __shfl_xor(wm, o, 64));
+        if ((threadIdx.x & 63) == 0 && wm >= 0) atomicMax(&best, wm);
     }
     __syncthreads();
     __shared__ uint32_t fin;
@@ -443,7 +446,12 @@ __device__ void level_step(SelState *sel, Hist *hist, int f)
         S += bs;
         C += bc;
     }
-    if (mine >= 0) atomicMax(&best, mine);
+    {
+        int wm = mine;  // one atomic per wavefront
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) wm = max(wm, __shfl_xor(wm, o, 64));
+        if ((threadIdx.x & 63) == 0 && wm >= 0) atomicMax(&best, wm);
+    }
     __syncthreads();
     int b = best;
     bool owner = b >= 0 && mine == b;
@@ -860,7 +868,14 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         const double S = aboveS + bs, C = aboveC + bc;  // values >= bin b's first edge
         const float eb = valid ? __uint_as_float(base + ((uint32_t)b << shift)) : 0.f;
         const double fb = S - (double)eb * C;
-        if (valid && fb >= radius) atomicMax(&best, b);
+        // highest bin with f(first edge) >= radius: bins run backwards over
+        // the lanes, so a wavefront's highest one sits in its lowest lane,
+        // and one LDS atomic per wavefront gives the block's (a thousand
+        // atomics on one word would queue for microseconds)
+        {
+            const unsigned long long hit = __ballot(valid && fb >= radius);
+            if (hit && (tid & 63) == __ffsll((long long)hit) - 1) atomicMax(&best, b);
+        }
         if (level == 0 && tid == 0) {
             // tau below the window: f(lo) < radius (every candidate is >= lo)
             if ((Sab + allS) - (double)s.win_lo * (Cab + allC) < radius) verdict = 2;
