@@ -172,7 +172,7 @@ struct CubeCommon {
     int capt;           // candidate capacity of one tile slice
     int ntiles;
     SweepGrid g;
-    int tile0;          // first tile of this cube in the launch's tile list
+    int tile0;          // first tile of this cube in the launch's full tile list
     int b0, nb;         // sweep B blocks of this cube: first, count
     float thr1;         // omega * step of w1
     float mu_lo, mu_hi;

@@ -183,8 +183,23 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
     __shared__ int tile0[kMaxBatch + 1];
     static_assert(sizeof(smem) >= 2 * kHistBins * 12, "LDS holds the search histograms");
 
-    for (int c = threadIdx.x; c <= sh.ncubes; c += NT)
-        tile0[c] = c < sh.ncubes ? cubes[c].c.tile0 : sh.total_tiles;
+    // The tiles of the cubes that work in this slot, one cube after another:
+    // a cube that idles takes none, so the persistent blocks, and the XCDs,
+    // share the working cubes' tiles evenly (with the full list, a batch in
+    // which a few cubes still run would leave most blocks without work).
+    // Every block reads the same flags, written before this launch.
+    static_assert(kMaxBatch <= 64, "one wavefront scans the cubes");
+    if (threadIdx.x < 64) {
+        const int c = threadIdx.x;
+        int x = c < sh.ncubes && !idle(cubes[c].c.sc) ? cubes[c].c.ntiles : 0;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (c >= o) x += y;
+        }
+        if (c < sh.ncubes) tile0[c + 1] = x;
+        if (c == 0) tile0[0] = 0;
+    }
     __syncthreads();
     const int tid = threadIdx.x;
     const int oti = tid / TJ, otj = tid % TJ;  // the thread's own point in the tile
@@ -203,7 +218,9 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
     const bool ring_w = tid < RING1, ring_u = tid < RINGU;
 
     for (int r = 0;; ++r) {
-        const int t = tile_at(blockIdx.x, sh.grid_a, sh.total_tiles, r);
+        // (the working cubes' tile count is read from LDS at each tile rather
+        // than kept live through the march)
+        const int t = tile_at(blockIdx.x, sh.grid_a, tile0[sh.ncubes], r);
         if (t < 0) break;
         int cube = 0;
         while (tile0[cube + 1] <= t) ++cube;
@@ -212,7 +229,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
         const int lt = __builtin_amdgcn_readfirstlane(t - tile0[cube]);  // tile within the cube
         const4<CubeArgs<DT>> &a = ((const4<CubeArgs<DT>> *)cubes)[cube];
         DevScalars *sc = a.c.sc;
-        if (idle(sc)) continue;
+        if (idle(sc)) continue;  // never taken: an idle cube has no tiles in the list
         const SweepGrid g{a.c.g.tj, a.c.g.ti, a.c.g.tk, a.c.g.kc};
         const int tj = lt % g.tj, rest = lt / g.tj;
         const int j0 = tj * TJ, i0 = (rest % g.ti) * TI, kb = (rest / g.ti) * g.kc;
