@@ -144,3 +144,30 @@ def test_band_chunk_raised_at_the_tile_limit():
         del ws
     assert np.array_equal(out[8], out[16])
     assert rel_l2(out[32], out[16]) <= 1e-6
+
+
+def test_working_cubes_share_the_persistent_blocks():
+    """Three cubes of 128 tiles each (8-band tiles): more tiles than resident
+    sweep A blocks, so the blocks take XCD-ordered tile ranges. One cube meets
+    its stopping rule early; from then on only the other two cubes' tiles are
+    in the list the blocks share. Every cube's iterates, iteration count and
+    stopping flag must still be those of the cube run alone."""
+    shapes = [(64, 64, 256), (64, 64, 250), (64, 60, 256)]
+    tols = [3e-3, 0.0, 0.0]
+    n_iter = 80
+    announce(f"batch {shapes}, tolerances {tols}, {n_iter} iterations, 8-band tiles")
+    torch_cuda()
+    import paper_2510_00562_amd as geo
+    cs = cubes(shapes, seed0=600)
+    st = [setup(geo, c, tol, band_chunk=8) for c, tol in zip(cs, tols)]
+    table = geo.Workspace(geo.geo_batch_table_size(len(cs)))
+    rc, res = geo.geo_batch_step([x[0] for x in st], [x[1] for x in st], [x[2] for x in st],
+                                 [x[3] for x in st], table, n_iter, use_graph=True)
+    states = [get_state(geo, d, p, ws, vd, c["v"].shape) for (d, p, vd, ws), c in zip(st, cs)]
+    assert res[0].converged and res[0].iters < n_iter - 20, res[0].iters  # stops near 37
+    assert [r.iters for r in res[1:]] == [n_iter, n_iter]
+    for c, tol, r, s in zip(cs, tols, res, states):
+        r1, s1 = run_solo(geo, c, n_iter, tol=tol, band_chunk=8)
+        assert r.iters == r1.iters and r.converged == r1.converged
+        assert r.tau_s == r1.tau_s and r.tau_t == r1.tau_t and r.r == r1.r
+        same(s, s1)
