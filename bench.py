@@ -474,7 +474,7 @@ def bench_realshape(args):
         p = geo.params(c["eps"], c["alpha"], c["beta"], omega=c["omega"], tol=1e-5)
         ws = geo.Workspace(geo.geo_workspace_size(d, p))
         table = geo.Workspace(geo.geo_batch_table_size(1))
-        kc, tune_ms = tune_band_chunk([d], [p], [v], [ws], table, candidates=(8, 16, 32))
+        kc, tune_ms = tune_band_chunk([d], [p], [v], [ws], table, candidates="auto")
         res = {}
         for label, chunk in (("tuned", kc), ("default", 0)):
             p.band_chunk = chunk

@@ -169,6 +169,25 @@ int geo_batch_step(int32_t n_cubes, const geo_dims *dims, const geo_params *p,
                    void *table, size_t table_bytes, int32_t n_iter, int32_t use_graph,
                    void *stream, geo_result *out);
 
+/* Launch geometry of the fused sweep (steps 1, 4, 5, 11, 12 of Alg. 1 and
+ * the inputs of steps 2 and 3), for callers that model load balance, such
+ * as a band-chunk autotuner. Host-side only: no GPU work.
+ *   requested: bands per tile asked for (0 = the default, 32); the library
+ *       uses at least 8 and doubles it until the cube has at most 4096 tiles.
+ *   used_chunk: the bands per tile the library will use.
+ *   tiles: tiles of this cube at that chunk (pixel tiles x band chunks).
+ *   tile_rows, tile_cols: pixel shape of a tile (n1 rows x n2 columns).
+ * Errors: GEO_EINVAL for bad dims, requested < 0 or a NULL output. */
+int geo_sweep_geometry(geo_dims dims, int32_t requested, int32_t *used_chunk, int32_t *tiles,
+                       int32_t *tile_rows, int32_t *tile_cols);
+
+/* Persistent blocks of the fused sweep on the current device: a launch
+ * runs min(blocks, tiles of all its cubes) blocks, and each block takes
+ * tiles in turn. dual_storage: GEO_STORE_F32 or GEO_STORE_BF16.
+ * Errors: GEO_EINVAL for a bad storage type or NULL output; GEO_EHIP
+ * without a usable device. */
+int geo_sweep_blocks(int32_t dual_storage, int32_t *blocks);
+
 /* State variables, for parity tests, checkpointing and resume. */
 enum {
     GEO_VAR_U = 0, GEO_VAR_S, GEO_VAR_T, GEO_VAR_W1, GEO_VAR_W2,

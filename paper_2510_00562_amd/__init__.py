@@ -101,6 +101,8 @@ def lib():
             "geo_project_box": [_vp, i64, d, d, _vp, _vp],
             "geo_strerror": [ctypes.c_int],
             "geo_batch_table_size": [i32, ctypes.POINTER(_sz)],
+            "geo_sweep_geometry": [geo_dims, i32] + [ctypes.POINTER(i32)] * 4,
+            "geo_sweep_blocks": [i32, ctypes.POINTER(i32)],
             "geo_batch_step": [i32, ctypes.POINTER(geo_dims), P, ctypes.POINTER(_vp),
                                ctypes.POINTER(_vp), ctypes.POINTER(_sz), _vp, _sz, i32, i32, _vp,
                                R],
@@ -236,6 +238,22 @@ def geo_solve(dims, p, v, u, s, t, ws: Workspace, stream=None) -> geo_result:
 def geo_batch_table_size(n_cubes: int) -> int:
     n = _sz()
     _check(lib().geo_batch_table_size(int(n_cubes), ctypes.byref(n)), "geo_batch_table_size")
+    return n.value
+
+
+def geo_sweep_geometry(dims, requested: int = 0):
+    """(bands per tile used, tiles, tile rows, tile columns) of the fused
+    sweep for one cube at the requested band chunk (0 = default)."""
+    out = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().geo_sweep_geometry(dims, int(requested), *[ctypes.byref(x) for x in out]),
+           "geo_sweep_geometry")
+    return tuple(x.value for x in out)
+
+
+def geo_sweep_blocks(dual_storage: int = GEO_STORE_F32) -> int:
+    """Persistent blocks of the fused sweep on the current device."""
+    n = ctypes.c_int32()
+    _check(lib().geo_sweep_blocks(int(dual_storage), ctypes.byref(n)), "geo_sweep_blocks")
     return n.value
 
 

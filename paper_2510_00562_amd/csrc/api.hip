@@ -353,6 +353,29 @@ int geo_batch_table_size(int32_t n_cubes, size_t *bytes)
     return GEO_OK;
 }
 
+int geo_sweep_geometry(geo_dims dims, int32_t requested, int32_t *used_chunk, int32_t *tiles,
+                       int32_t *tile_rows, int32_t *tile_cols)
+{
+    if (!dims_ok(dims) || requested < 0 || !used_chunk || !tiles || !tile_rows || !tile_cols)
+        return GEO_EINVAL;
+    const int kc = band_chunk(dims.n1, dims.n2, dims.n3, requested);
+    *used_chunk = kc;
+    *tiles = sweep_grid(dims.n1, dims.n2, dims.n3, kc).blocks();
+    *tile_rows = kTI;
+    *tile_cols = kTJ;
+    return GEO_OK;
+}
+
+int geo_sweep_blocks(int32_t dual_storage, int32_t *blocks)
+{
+    if ((dual_storage != GEO_STORE_F32 && dual_storage != GEO_STORE_BF16) || !blocks) return GEO_EINVAL;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return GEO_EHIP;
+    // the persistent grid of a launch with at least this many tiles
+    *blocks = sweep_a_grid(dual_storage == GEO_STORE_BF16 ? 2 : 4, 1 << 30);
+    return GEO_OK;
+}
+
 int geo_batch_step(int32_t n_cubes, const geo_dims *dims, const geo_params *p,
                    const float *const *v, void *const *ws, const size_t *ws_bytes, void *table,
                    size_t table_bytes, int32_t n_iter, int32_t use_graph, void *stream,

@@ -50,3 +50,23 @@ def test_strerror_and_argument_checks_without_gpu():
     fake = ctypes.c_void_p(256)
     assert L.geo_state_init(geo.geo_dims(4, 4, 4), ctypes.byref(p), fake, None, 0, None) == -2
     assert L.geo_apply_op(42, 0, geo.geo_dims(4, 4, 4), fake, fake, None) == -1
+
+
+def test_sweep_geometry_is_host_side():
+    """Tile counts of the fused sweep (8 x 128 pixel tiles): 256 x 256 x 128
+    at the default 32 bands gives 32 x 2 x 4 tiles; 512 x 512 x 224 at 8
+    bands would need 7168 tiles, beyond the 4096 a cube may have, so the
+    chunk is doubled to 16 (3584 tiles); requests below 8 bands use 8."""
+    import paper_2510_00562_amd as geo
+    g = geo.geo_sweep_geometry(geo.dims_of((128, 256, 256)))
+    assert g == (32, 256, 8, 128)
+    assert geo.geo_sweep_geometry(geo.dims_of((224, 512, 512)), 8)[:2] == (16, 3584)
+    assert geo.geo_sweep_geometry(geo.dims_of((360, 100, 100)), 3)[:2] == (8, 13 * 1 * 45)
+    assert geo.geo_sweep_geometry(geo.dims_of((1, 1, 1)), 0)[:2] == (32, 1)
+    L = geo.lib()
+    x = ctypes.c_int32()
+    assert L.geo_sweep_geometry(geo.geo_dims(0, 4, 4), 0, *[ctypes.byref(x)] * 4) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), -1, *[ctypes.byref(x)] * 4) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 0, None, *[ctypes.byref(x)] * 3) == -1
+    assert L.geo_sweep_blocks(7, ctypes.byref(x)) == -1
+    assert L.geo_sweep_blocks(0, None) == -1
