@@ -78,10 +78,13 @@ typedef struct {
                             whatever this is, since the device stops
                             iterating on its own once the rule is met      */
     int32_t band_chunk;  /* bands each tile of the fused sweep marches
-                            through (0 = 32; values below 8 count as 8; raised
-                            when a cube would have more than 4096 tiles). A
-                            performance knob only: results do not depend on
-                            it beyond FP64 summation order.               */
+                            through (0 = chosen per cube: the depth in 8..32
+                            whose tiles the device's persistent blocks finish
+                            first, see geo_sweep_geometry; values below 8
+                            count as 8; raised when a cube would have more
+                            than 4096 tiles). A performance knob only:
+                            results do not depend on it beyond FP64
+                            summation order.                              */
 } geo_params;
 
 typedef struct {
@@ -172,14 +175,19 @@ int geo_batch_step(int32_t n_cubes, const geo_dims *dims, const geo_params *p,
 /* Launch geometry of the fused sweep (steps 1, 4, 5, 11, 12 of Alg. 1 and
  * the inputs of steps 2 and 3), for callers that model load balance, such
  * as a band-chunk autotuner. Host-side only: no GPU work.
- *   requested: bands per tile asked for (0 = the default, 32); the library
- *       uses at least 8 and doubles it until the cube has at most 4096 tiles.
+ *   requested: bands per tile asked for; the library uses at least 8 and
+ *       doubles it until the cube has at most 4096 tiles. 0 = the default:
+ *       the depth kc in 8..32 that minimises ceil(tiles / blocks) x
+ *       (min(kc, n3) + 2), ties to the deeper one.
+ *   blocks: persistent blocks the default is chosen for (geo_sweep_blocks
+ *       on the device that will run the cube); read only when requested = 0.
  *   used_chunk: the bands per tile the library will use.
  *   tiles: tiles of this cube at that chunk (pixel tiles x band chunks).
  *   tile_rows, tile_cols: pixel shape of a tile (n1 rows x n2 columns).
- * Errors: GEO_EINVAL for bad dims, requested < 0 or a NULL output. */
-int geo_sweep_geometry(geo_dims dims, int32_t requested, int32_t *used_chunk, int32_t *tiles,
-                       int32_t *tile_rows, int32_t *tile_cols);
+ * Errors: GEO_EINVAL for bad dims, requested < 0, requested = 0 with
+ * blocks < 1, or a NULL output. */
+int geo_sweep_geometry(geo_dims dims, int32_t requested, int32_t blocks, int32_t *used_chunk,
+                       int32_t *tiles, int32_t *tile_rows, int32_t *tile_cols);
 
 /* Persistent blocks of the fused sweep on the current device: a launch
  * runs min(blocks, tiles of all its cubes) blocks, and each block takes

@@ -353,12 +353,13 @@ int geo_batch_table_size(int32_t n_cubes, size_t *bytes)
     return GEO_OK;
 }
 
-int geo_sweep_geometry(geo_dims dims, int32_t requested, int32_t *used_chunk, int32_t *tiles,
-                       int32_t *tile_rows, int32_t *tile_cols)
+int geo_sweep_geometry(geo_dims dims, int32_t requested, int32_t blocks, int32_t *used_chunk,
+                       int32_t *tiles, int32_t *tile_rows, int32_t *tile_cols)
 {
-    if (!dims_ok(dims) || requested < 0 || !used_chunk || !tiles || !tile_rows || !tile_cols)
+    if (!dims_ok(dims) || requested < 0 || (requested == 0 && blocks < 1) || !used_chunk || !tiles ||
+        !tile_rows || !tile_cols)
         return GEO_EINVAL;
-    const int kc = band_chunk(dims.n1, dims.n2, dims.n3, requested);
+    const int kc = band_chunk(dims.n1, dims.n2, dims.n3, requested, blocks);
     *used_chunk = kc;
     *tiles = sweep_grid(dims.n1, dims.n2, dims.n3, kc).blocks();
     *tile_rows = kTI;

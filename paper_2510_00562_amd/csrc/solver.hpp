@@ -119,11 +119,39 @@ inline SweepGrid sweep_grid(int n1, int n2, int n3, int kc)
 {
     return SweepGrid{ceil_div(n2, kTJ), ceil_div(n1, kTI), ceil_div(n3, kc), kc};
 }
-// Bands per tile actually used: the request (0 = default), raised until the
-// cube has at most kMaxTiles tiles.
-inline int band_chunk(int n1, int n2, int n3, int requested)
+// Fixed work of one tile (its halo band, the pipeline fill, its partial
+// sums) in band-equivalents, for the load-balance rule below.
+constexpr double kTileFixedBands = 2.0;
+// Default depth for a cube: the chunk in [kMinKC, kDefaultKC] whose tiles,
+// taken in turn by `blocks` persistent blocks, finish first. A round of
+// tiles costs the deepest tile's bands plus the fixed work; ties keep the
+// deeper chunk (fewer tiles). A cube with few tiles gets shallower chunks,
+// so that more blocks work on it, and a tile count just past a multiple of
+// the blocks is avoided. blocks <= 0: kDefaultKC.
+inline int default_chunk(int n1, int n2, int n3, int blocks)
 {
-    int kc = requested > 0 ? requested : kDefaultKC;
+    if (blocks <= 0) return kDefaultKC;
+    int best = kDefaultKC;
+    double best_cost = 0.0;
+    for (int kc = kDefaultKC; kc >= kMinKC; --kc) {
+        const SweepGrid g = sweep_grid(n1, n2, n3, kc);
+        const int T = g.blocks();
+        if (T > kMaxTiles) break;  // shallower chunks only add tiles
+        const int G = blocks < T ? blocks : T;
+        const double cost = (double)ceil_div(T, G) * ((kc < n3 ? kc : n3) + kTileFixedBands);
+        if (kc == kDefaultKC || cost < best_cost - 1e-9) {
+            best = kc;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+// Bands per tile actually used: the request (0 = the default above for
+// `blocks` persistent blocks), at least kMinKC, raised until the cube has at
+// most kMaxTiles tiles.
+inline int band_chunk(int n1, int n2, int n3, int requested, int blocks)
+{
+    int kc = requested > 0 ? requested : default_chunk(n1, n2, n3, blocks);
     if (kc < kMinKC) kc = kMinKC;
     while (sweep_grid(n1, n2, n3, kc).blocks() > kMaxTiles) kc *= 2;
     return kc;
@@ -136,7 +164,7 @@ inline int sweep_b_blocks(int64_t n)
 }
 inline int max_tiles(int n1, int n2, int n3)
 {
-    return sweep_grid(n1, n2, n3, band_chunk(n1, n2, n3, kMinKC)).blocks();
+    return sweep_grid(n1, n2, n3, band_chunk(n1, n2, n3, kMinKC, 0)).blocks();
 }
 
 Layout make_layout(int n1, int n2, int n3, int dual_storage);

@@ -976,7 +976,7 @@ void cube_entry_t(CubeArgs<DT> *a, const Dims &d, const float *v, void *ws, cons
     c.hist = (Hist *)(b + L.hist);
     c.cand = (float *)(b + L.cand);
     c.ccount = (uint32_t *)(b + L.ccount);
-    c.g = sweep_grid(d.n1, d.n2, d.n3, band_chunk(d.n1, d.n2, d.n3, kc));
+    c.g = sweep_grid(d.n1, d.n2, d.n3, band_chunk(d.n1, d.n2, d.n3, kc, sweep_a_grid(sizeof(DT), 1 << 30)));
     c.ntiles = c.g.blocks();
     c.capt = (int)(L.cap / c.ntiles);
     c.tile0 = tile0;

@@ -4,6 +4,8 @@ import ctypes
 import os
 import re
 
+import pytest
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -54,19 +56,58 @@ def test_strerror_and_argument_checks_without_gpu():
 
 def test_sweep_geometry_is_host_side():
     """Tile counts of the fused sweep (8 x 128 pixel tiles): 256 x 256 x 128
-    at the default 32 bands gives 32 x 2 x 4 tiles; 512 x 512 x 224 at 8
-    bands would need 7168 tiles, beyond the 4096 a cube may have, so the
-    chunk is doubled to 16 (3584 tiles); requests below 8 bands use 8."""
+    at 32 bands gives 32 x 2 x 4 tiles; 512 x 512 x 224 at 8 bands would
+    need 7168 tiles, beyond the 4096 a cube may have, so the chunk is
+    doubled to 16 (3584 tiles); requests below 8 bands use 8."""
     import paper_2510_00562_amd as geo
-    g = geo.geo_sweep_geometry(geo.dims_of((128, 256, 256)))
+    g = geo.geo_sweep_geometry(geo.dims_of((128, 256, 256)), 32)
     assert g == (32, 256, 8, 128)
     assert geo.geo_sweep_geometry(geo.dims_of((224, 512, 512)), 8)[:2] == (16, 3584)
     assert geo.geo_sweep_geometry(geo.dims_of((360, 100, 100)), 3)[:2] == (8, 13 * 1 * 45)
-    assert geo.geo_sweep_geometry(geo.dims_of((1, 1, 1)), 0)[:2] == (32, 1)
     L = geo.lib()
     x = ctypes.c_int32()
-    assert L.geo_sweep_geometry(geo.geo_dims(0, 4, 4), 0, *[ctypes.byref(x)] * 4) == -1
-    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), -1, *[ctypes.byref(x)] * 4) == -1
-    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 0, None, *[ctypes.byref(x)] * 3) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(0, 4, 4), 8, 256, *[ctypes.byref(x)] * 4) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), -1, 256, *[ctypes.byref(x)] * 4) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 0, 0, *[ctypes.byref(x)] * 4) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 8, 256, None, *[ctypes.byref(x)] * 3) == -1
     assert L.geo_sweep_blocks(7, ctypes.byref(x)) == -1
     assert L.geo_sweep_blocks(0, None) == -1
+
+
+@pytest.mark.parametrize("shape, blocks, chunk", [
+    # (N3, N1, N2): 256 tiles at 32 bands fill 256 blocks in one round
+    ((128, 256, 256), 256, 32),
+    # 7 rounds of 32 + 2 band-equivalents; 28 bands would need 8 of 30
+    ((224, 512, 512), 256, 32),
+    # 384 tiles at 32 bands are 1.5 rounds: 24 bands give 2 rounds of 512
+    # tiles of 24 + 2 (27 bands would give 2 rounds of 29, with a last
+    # chunk of one band)
+    ((190, 256, 256), 256, 24),
+    # 32 tiles at 32 bands on 256 blocks: 8 bands give 128 tiles, each 4x shorter
+    ((64, 128, 128), 256, 8),
+    # 13 tile rows: 19 chunks of at most 19 bands give 247 tiles, one round
+    ((360, 100, 100), 256, 19),
+    # 15 tile rows: 17 chunks of at most 12 bands give 255 tiles, one round
+    ((198, 120, 120), 256, 12),
+    # 8 tile rows, 16 bands: 8 tiles of 16 (+2) or 16 tiles of 8 (+2)
+    ((16, 64, 64), 256, 8),
+    # a single 5-band tile at any depth: ties keep 32
+    ((5, 8, 100), 256, 32),
+    # fewer blocks: 256 x 256 x 128 on 64 blocks still prefers 32 bands
+    ((128, 256, 256), 64, 32),
+])
+def test_default_band_chunk_balances_the_blocks(shape, blocks, chunk):
+    """The library's default depth (band_chunk 0) minimises
+    ceil(tiles / blocks) x (min(kc, N3) + 2) over kc in 8..32, ties to the
+    deeper chunk."""
+    import paper_2510_00562_amd as geo
+    d = geo.dims_of(shape)
+    used = geo.geo_sweep_geometry(d, 0, blocks)[0]
+    assert used == chunk
+    # brute force of the same rule from the tile counts the library reports
+    cost = {}
+    for kc in range(32, 7, -1):
+        u, tiles, _, _ = geo.geo_sweep_geometry(d, kc)
+        if u == kc:  # a raised chunk repeats a deeper one
+            cost[kc] = -(-tiles // min(blocks, tiles)) * (min(kc, shape[0]) + 2)
+    assert used == min(cost, key=lambda kc: (cost[kc], -kc))
