@@ -277,7 +277,7 @@ def bench_batch(args):
         wss.append(geo.Workspace(geo.geo_workspace_size(d, p)))
     total = sum(v.numel() for v in vs)
     table = geo.Workspace(geo.geo_batch_table_size(len(vs)))
-    kc, tune_ms = tune_band_chunk(dims, ps, vs, wss, table)
+    kc, tune_ms = tune_band_chunk(dims, ps, vs, wss, table, candidates=(16, 24, 32))
     K, W = args.steps, args.warmup
 
     # per-cube loop: each cube alone, one after the other
@@ -476,15 +476,17 @@ def bench_realshape(args):
         table = geo.Workspace(geo.geo_batch_table_size(1))
         kc, tune_ms = tune_band_chunk([d], [p], [v], [ws], table, candidates="auto")
         res = {}
-        for label, chunk in (("tuned", kc), ("default", 0)):
+        # tuned; the library's per-cube default (band_chunk 0); a fixed 32
+        for label, chunk in (("tuned", kc), ("default", 0), ("fixed_32", 32)):
             p.band_chunk = chunk
+            used = geo.geo_sweep_geometry(d, chunk, geo.geo_sweep_blocks(p.dual_storage))[0]
             geo.geo_state_init(d, p, v, ws)
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             r = geo.geo_step(d, p, v, ws, 20000)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
-            res[label] = {"band_chunk": chunk or 32, "iters": r.iters, "seconds": el,
+            res[label] = {"band_chunk": used, "iters": r.iters, "seconds": el,
                           "voxel_iterations_per_s": v.numel() * r.iters / el,
                           "converged": bool(r.converged)}
         u = torch.empty_like(v)
