@@ -152,11 +152,12 @@ int geo_solve(geo_dims dims, const geo_params *p, const float *v,
 /* Batched iterations: n_cubes independent solver states (cubes of any sizes,
  * each initialised by geo_state_init in its own workspace) advanced together,
  * one launch sequence per iteration for all of them: the fused sweep runs
- * persistently over the concatenated tiles of every cube, the threshold
- * search and the finalisation take one block per cube and field. Each cube
- * does n_iter iterations of Alg. 1 or stops earlier by its own rule (eq.
- * (28), its p[c].tol); a cube that is done idles while the others go on, so
- * every cube's iterates are exactly those geo_step would give it alone.
+ * persistently over the concatenated tiles of the cubes still working, the
+ * threshold search and the finalisation take one block per cube and field.
+ * Each cube does n_iter iterations of Alg. 1 or stops earlier by its own
+ * rule (eq. (28), its p[c].tol); a cube that is done idles while the others
+ * go on, so every cube's iterates are exactly those geo_step would give it
+ * alone.
  *   dims, p, v, ws, ws_bytes, out: HOST arrays of n_cubes entries (v[c] and
  *       ws[c] are device pointers); every p[c].dual_storage must be equal.
  *   table: device buffer of geo_batch_table_size bytes (256-byte aligned)

@@ -98,7 +98,7 @@ struct Layout {
 #define GEO_SWEEP_B_ROWS 2
 #endif
 constexpr int kTI = GEO_TILE_ROWS, kTJ = GEO_TILE_COLS, kSweepThreads = kTI * kTJ;
-constexpr int kDefaultKC = 32;       // bands per tile unless the caller picks
+constexpr int kDefaultKC = 32;       // deepest default chunk (the rule below picks 8..32)
 constexpr int kMinKC = 8;
 constexpr int kMaxTiles = 4096;      // tiles of one cube (slices of its search)
 constexpr int kMaxBatch = 64;        // cubes of one batched launch
@@ -185,9 +185,10 @@ struct Side {
 
 // Everything the iteration kernels need about one cube. A launch covers a
 // table of these in device memory (one entry for a single cube, up to
-// kMaxBatch for a batch): sweep A walks the concatenated tile list, the
-// search takes one block per (cube, field), sweep B a block range per cube
-// and the finalize one block per cube. Stopped cubes are skipped.
+// kMaxBatch for a batch): sweep A walks the concatenated tile list of the
+// cubes still working, the search takes one block per (cube, field), sweep B
+// a block range per cube and the finalize one block per cube. Stopped cubes
+// are skipped.
 struct CubeCommon {
     Dims d;
     const float *v;
