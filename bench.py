@@ -483,7 +483,8 @@ def bench_realshape(args):
         # tuned; the library's per-cube default (band_chunk 0); a fixed 32
         for label, chunk in (("tuned", kc), ("default", 0), ("fixed_32", 32)):
             p.band_chunk = chunk
-            used = geo.geo_sweep_geometry(d, chunk, geo.geo_sweep_blocks(p.dual_storage))[0]
+            used = geo.geo_sweep_geometry(d, chunk, geo.geo_sweep_blocks(p.dual_storage),
+                                          p.dual_storage)[0]
             geo.geo_state_init(d, p, v, ws)
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -176,6 +176,9 @@ int geo_batch_step(int32_t n_cubes, const geo_dims *dims, const geo_params *p,
 /* Launch geometry of the fused sweep (steps 1, 4, 5, 11, 12 of Alg. 1 and
  * the inputs of steps 2 and 3), for callers that model load balance, such
  * as a band-chunk autotuner. Host-side only: no GPU work.
+ *   dual_storage: GEO_STORE_F32 or GEO_STORE_BF16 (as in geo_params). A
+ *       tile is 8 x 128 pixels, or 16 x 64 when the cube's width fills a
+ *       64-wide tile grid more than 3% better (FP32 duals only).
  *   requested: bands per tile asked for; the library uses at least 8 and
  *       doubles it until the cube has at most 4096 tiles. 0 = the default:
  *       the depth kc in 8..32 that minimises ceil(tiles / blocks) x
@@ -185,10 +188,11 @@ int geo_batch_step(int32_t n_cubes, const geo_dims *dims, const geo_params *p,
  *   used_chunk: the bands per tile the library will use.
  *   tiles: tiles of this cube at that chunk (pixel tiles x band chunks).
  *   tile_rows, tile_cols: pixel shape of a tile (n1 rows x n2 columns).
- * Errors: GEO_EINVAL for bad dims, requested < 0, requested = 0 with
- * blocks < 1, or a NULL output. */
-int geo_sweep_geometry(geo_dims dims, int32_t requested, int32_t blocks, int32_t *used_chunk,
-                       int32_t *tiles, int32_t *tile_rows, int32_t *tile_cols);
+ * Errors: GEO_EINVAL for bad dims or storage type, requested < 0,
+ * requested = 0 with blocks < 1, or a NULL output. */
+int geo_sweep_geometry(geo_dims dims, int32_t dual_storage, int32_t requested, int32_t blocks,
+                       int32_t *used_chunk, int32_t *tiles, int32_t *tile_rows,
+                       int32_t *tile_cols);
 
 /* Persistent blocks of the fused sweep on the current device: a launch
  * runs min(blocks, tiles of all its cubes) blocks, and each block takes

@@ -101,7 +101,7 @@ def lib():
             "geo_project_box": [_vp, i64, d, d, _vp, _vp],
             "geo_strerror": [ctypes.c_int],
             "geo_batch_table_size": [i32, ctypes.POINTER(_sz)],
-            "geo_sweep_geometry": [geo_dims, i32, i32] + [ctypes.POINTER(i32)] * 4,
+            "geo_sweep_geometry": [geo_dims, i32, i32, i32] + [ctypes.POINTER(i32)] * 4,
             "geo_sweep_blocks": [i32, ctypes.POINTER(i32)],
             "geo_batch_step": [i32, ctypes.POINTER(geo_dims), P, ctypes.POINTER(_vp),
                                ctypes.POINTER(_vp), ctypes.POINTER(_sz), _vp, _sz, i32, i32, _vp,
@@ -241,12 +241,13 @@ def geo_batch_table_size(n_cubes: int) -> int:
     return n.value
 
 
-def geo_sweep_geometry(dims, requested: int = 0, blocks: int = 0):
+def geo_sweep_geometry(dims, requested: int = 0, blocks: int = 0,
+                       dual_storage: int = GEO_STORE_F32):
     """(bands per tile used, tiles, tile rows, tile columns) of the fused
     sweep for one cube at the requested band chunk (0 = the library's
     default for `blocks` persistent blocks)."""
     out = [ctypes.c_int32() for _ in range(4)]
-    _check(lib().geo_sweep_geometry(dims, int(requested), int(blocks),
+    _check(lib().geo_sweep_geometry(dims, int(dual_storage), int(requested), int(blocks),
                                     *[ctypes.byref(x) for x in out]), "geo_sweep_geometry")
     return tuple(x.value for x in out)
 

@@ -183,15 +183,19 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
     if (!table || ((uintptr_t)table & 255u) || table_bytes < (size_t)n * sizeof(CubeEntry))
         return GEO_EWORKSPACE;
     std::vector<CubeEntry> ent(n);
-    LaunchShape sh{n, 0, 0, 0};
+    LaunchShape sh{};
+    sh.ncubes = n;
     for (int c = 0; c < n; ++c) {
         int nt = 0, nb = 0;
         cube_entry(&ent[c], to_dims(dims[c]), v[c], ws[c], L[c], p[c].omega, p[c].mu_lo, p[c].mu_hi,
                    p[c].band_chunk, sh.total_tiles, sh.total_b, &nt, &nb);
         sh.total_tiles += nt;
         sh.total_b += nb;
+        sh.shape_tiles[tile_shape(dims[c].n1, dims[c].n2, L[c].dual_bytes)] += nt;
     }
     sh.grid_a = sweep_a_grid(L[0].dual_bytes, sh.total_tiles);
+    for (int q = 0; q < kTileShapes; ++q)
+        sh.shape_grid[q] = sh.shape_tiles[q] > 0 ? sweep_a_grid(L[0].dual_bytes, sh.shape_tiles[q]) : 0;
     int rc = hip_status(hipMemcpyAsync(table, ent.data(), (size_t)n * sizeof(CubeEntry),
                                        hipMemcpyHostToDevice, st));
     for (int c = 0; c < n && !rc; ++c)
@@ -353,17 +357,19 @@ int geo_batch_table_size(int32_t n_cubes, size_t *bytes)
     return GEO_OK;
 }
 
-int geo_sweep_geometry(geo_dims dims, int32_t requested, int32_t blocks, int32_t *used_chunk,
-                       int32_t *tiles, int32_t *tile_rows, int32_t *tile_cols)
+int geo_sweep_geometry(geo_dims dims, int32_t dual_storage, int32_t requested, int32_t blocks,
+                       int32_t *used_chunk, int32_t *tiles, int32_t *tile_rows, int32_t *tile_cols)
 {
-    if (!dims_ok(dims) || requested < 0 || (requested == 0 && blocks < 1) || !used_chunk || !tiles ||
-        !tile_rows || !tile_cols)
+    if (!dims_ok(dims) || (dual_storage != GEO_STORE_F32 && dual_storage != GEO_STORE_BF16) ||
+        requested < 0 || (requested == 0 && blocks < 1) || !used_chunk || !tiles || !tile_rows ||
+        !tile_cols)
         return GEO_EINVAL;
-    const int kc = band_chunk(dims.n1, dims.n2, dims.n3, requested, blocks);
+    const int shape = tile_shape(dims.n1, dims.n2, dual_storage == GEO_STORE_BF16 ? 2 : 4);
+    const int kc = band_chunk(dims.n1, dims.n2, dims.n3, requested, blocks, shape);
     *used_chunk = kc;
-    *tiles = sweep_grid(dims.n1, dims.n2, dims.n3, kc).blocks();
-    *tile_rows = kTI;
-    *tile_cols = kTJ;
+    *tiles = sweep_grid(dims.n1, dims.n2, dims.n3, kc, shape).blocks();
+    *tile_rows = kShapeTI[shape];
+    *tile_cols = kShapeTJ[shape];
     return GEO_OK;
 }
 

@@ -85,19 +85,20 @@ struct Layout {
 
 // Tile of the fused primal/dual sweep: TI x TJ pixels (one per thread of a
 // 1024-thread workgroup), marching through a chunk of kc bands (kc chosen
-// per cube at run time). 8 x 128 tiles read each band row of a tile as one
-// 512-byte run per array; they streamed 2.5% faster than 16 x 64 tiles in a
-// probe of the same 22-read, 18-write access pattern.
-#ifndef GEO_TILE_ROWS
-#define GEO_TILE_ROWS 8
-#endif
-#ifndef GEO_TILE_COLS
-#define GEO_TILE_COLS 128
-#endif
+// per cube at run time). Two shapes, chosen per cube by its width:
+//   shape 0, 8 x 128: each band row of a tile is one 512-byte run per array;
+//     it streamed 2.5% faster than 16 x 64 in a probe of the same 22-read,
+//     18-write access pattern;
+//   shape 1, 16 x 64: for widths that leave much of a 128-column tile
+//     outside the cube (N2 = 160: 37.5% of the lanes of two 128-wide tiles,
+//     17% of three 64-wide ones). Idle lanes cost time, since the sweep's
+//     rate is set by its loads in flight.
 #ifndef GEO_SWEEP_B_ROWS
 #define GEO_SWEEP_B_ROWS 2
 #endif
-constexpr int kTI = GEO_TILE_ROWS, kTJ = GEO_TILE_COLS, kSweepThreads = kTI * kTJ;
+constexpr int kTileShapes = 2;
+constexpr int kShapeTI[kTileShapes] = {8, 16}, kShapeTJ[kTileShapes] = {128, 64};
+constexpr int kSweepThreads = 1024;
 constexpr int kDefaultKC = 32;       // deepest default chunk (the rule below picks 8..32)
 constexpr int kMinKC = 8;
 constexpr int kMaxTiles = 4096;      // tiles of one cube (slices of its search)
@@ -111,13 +112,29 @@ constexpr int kTimedEvery = 8;  // geo_step_timed: events around every 8th sweep
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
 
+// Tile shape of a cube: 16 x 64 when its share of tile points inside the
+// cube beats that of 8 x 128 by more than 3% (the streaming advantage of the
+// wider tile), else 8 x 128. With BF16 duals always 8 x 128 (the 16 x 64
+// sweep spills registers in that form). A function of the cube's size and
+// storage only, so a cube runs the same tiles alone and in a batch.
+inline double tile_fill(int n1, int n2, int shape)
+{
+    const int ti = kShapeTI[shape], tj = kShapeTJ[shape];
+    return ((double)n1 / (ti * ceil_div(n1, ti))) * ((double)n2 / (tj * ceil_div(n2, tj)));
+}
+inline int tile_shape(int n1, int n2, int dual_bytes)
+{
+    return dual_bytes == 4 && tile_fill(n1, n2, 1) > 1.03 * tile_fill(n1, n2, 0) ? 1 : 0;
+}
 struct SweepGrid {
     int tj, ti, tk, kc;  // tiles along j, i, band chunks; bands per chunk
+    int shape;           // tile shape (kShapeTI/kShapeTJ)
     __host__ __device__ int blocks() const { return tj * ti * tk; }
 };
-inline SweepGrid sweep_grid(int n1, int n2, int n3, int kc)
+inline SweepGrid sweep_grid(int n1, int n2, int n3, int kc, int shape)
 {
-    return SweepGrid{ceil_div(n2, kTJ), ceil_div(n1, kTI), ceil_div(n3, kc), kc};
+    return SweepGrid{ceil_div(n2, kShapeTJ[shape]), ceil_div(n1, kShapeTI[shape]), ceil_div(n3, kc), kc,
+                     shape};
 }
 // Fixed work of one tile (its halo band, the pipeline fill, its partial
 // sums) in band-equivalents, for the load-balance rule below.
@@ -128,13 +145,13 @@ constexpr double kTileFixedBands = 2.0;
 // deeper chunk (fewer tiles). A cube with few tiles gets shallower chunks,
 // so that more blocks work on it, and a tile count just past a multiple of
 // the blocks is avoided. blocks <= 0: kDefaultKC.
-inline int default_chunk(int n1, int n2, int n3, int blocks)
+inline int default_chunk(int n1, int n2, int n3, int blocks, int shape)
 {
     if (blocks <= 0) return kDefaultKC;
     int best = kDefaultKC;
     double best_cost = 0.0;
     for (int kc = kDefaultKC; kc >= kMinKC; --kc) {
-        const SweepGrid g = sweep_grid(n1, n2, n3, kc);
+        const SweepGrid g = sweep_grid(n1, n2, n3, kc, shape);
         const int T = g.blocks();
         if (T > kMaxTiles) break;  // shallower chunks only add tiles
         const int G = blocks < T ? blocks : T;
@@ -149,11 +166,11 @@ inline int default_chunk(int n1, int n2, int n3, int blocks)
 // Bands per tile actually used: the request (0 = the default above for
 // `blocks` persistent blocks), at least kMinKC, raised until the cube has at
 // most kMaxTiles tiles.
-inline int band_chunk(int n1, int n2, int n3, int requested, int blocks)
+inline int band_chunk(int n1, int n2, int n3, int requested, int blocks, int shape)
 {
-    int kc = requested > 0 ? requested : default_chunk(n1, n2, n3, blocks);
+    int kc = requested > 0 ? requested : default_chunk(n1, n2, n3, blocks, shape);
     if (kc < kMinKC) kc = kMinKC;
-    while (sweep_grid(n1, n2, n3, kc).blocks() > kMaxTiles) kc *= 2;
+    while (sweep_grid(n1, n2, n3, kc, shape).blocks() > kMaxTiles) kc *= 2;
     return kc;
 }
 inline int point_blocks(int64_t n) { return ceil_div(n, kPointThreads); }
@@ -164,7 +181,12 @@ inline int sweep_b_blocks(int64_t n)
 }
 inline int max_tiles(int n1, int n2, int n3)
 {
-    return sweep_grid(n1, n2, n3, band_chunk(n1, n2, n3, kMinKC, 0)).blocks();
+    int m = 0;  // either tile shape
+    for (int q = 0; q < kTileShapes; ++q) {
+        const int t = sweep_grid(n1, n2, n3, band_chunk(n1, n2, n3, kMinKC, 0, q), q).blocks();
+        m = t > m ? t : m;
+    }
+    return m;
 }
 
 Layout make_layout(int n1, int n2, int n3, int dual_storage);
@@ -255,6 +277,8 @@ struct LaunchShape {
     int total_tiles;  // sweep A tiles over all cubes
     int grid_a;       // persistent sweep A blocks
     int total_b;      // sweep B blocks over all cubes
+    int shape_tiles[kTileShapes];  // sweep A tiles of the cubes of each tile shape
+    int shape_grid[kTileShapes];   // persistent blocks of the sweep A launch of each shape
 };
 
 // Host image of one cube's table entry (FP32 or BF16 duals: same size).

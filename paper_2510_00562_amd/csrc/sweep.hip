@@ -34,15 +34,29 @@ namespace geo {
 
 namespace {
 
-constexpr int TI = kTI, TJ = kTJ, NT = kSweepThreads;
-constexpr int H2 = TI + 4, W2 = TJ + 4, S2 = H2 * W2;  // y with a 2-pixel halo
-constexpr int H1 = TI + 2, W1 = TJ + 2, S1 = H1 * W1;  // w' on a 1-pixel ring
-constexpr int HU = TI + 1, WU = TJ + 1, SU = HU * WU;  // u' with the (+1, +1) ring
-constexpr int NY = (S2 + NT - 1) / NT;                  // y points per thread
-constexpr int RING1 = S1 - TI * TJ;                     // w' ring points
-constexpr int RINGU = SU - TI * TJ;                     // u' ring points
-static_assert(TI * TJ == NT && TJ % 64 == 0, "one own point per thread, whole wavefronts per tile row");
-static_assert(RING1 <= NT && RINGU <= NT, "at most one ring point per thread");
+constexpr int NT = kSweepThreads;
+// Tile geometry of shape S (kShapeTI[S] x kShapeTJ[S] pixels)
+template <int S>
+struct TileOf {
+    static constexpr int TI = kShapeTI[S], TJ = kShapeTJ[S];
+    static constexpr int H2 = TI + 4, W2 = TJ + 4, S2 = H2 * W2;  // y with a 2-pixel halo
+    static constexpr int H1 = TI + 2, W1 = TJ + 2, S1 = H1 * W1;  // w' on a 1-pixel ring
+    static constexpr int HU = TI + 1, WU = TJ + 1, SU = HU * WU;  // u' with the (+1, +1) ring
+    static constexpr int NY = (S2 + NT - 1) / NT;                  // y points per thread
+    static constexpr int RING1 = S1 - TI * TJ;                     // w' ring points
+    static constexpr int RINGU = SU - TI * TJ;                     // u' ring points
+    static_assert(TI * TJ == NT && TJ % 64 == 0, "one own point per thread, whole wavefronts per tile row");
+    static_assert(RING1 <= NT && RINGU <= NT, "at most one ring point per thread");
+};
+// the geometry of shape S under its short names, inside a kernel
+#define GEO_TILE_GEOMETRY(S)                                                              \
+    constexpr int TI = TileOf<S>::TI, TJ = TileOf<S>::TJ;                                 \
+    constexpr int H2 = TileOf<S>::H2, W2 = TileOf<S>::W2, S2 = TileOf<S>::S2;             \
+    constexpr int H1 = TileOf<S>::H1, W1 = TileOf<S>::W1, S1 = TileOf<S>::S1;             \
+    constexpr int HU = TileOf<S>::HU, WU = TileOf<S>::WU, SU = TileOf<S>::SU;             \
+    constexpr int NY = TileOf<S>::NY, RING1 = TileOf<S>::RING1, RINGU = TileOf<S>::RINGU; \
+    (void)H2; (void)W2; (void)S2; (void)H1; (void)W1; (void)S1;                          \
+    (void)HU; (void)WU; (void)SU; (void)NY; (void)RING1; (void)RINGU
 constexpr int NPT = 256;  // threads of the pointwise kernels
 
 template <typename DT>
@@ -94,9 +108,10 @@ __device__ __forceinline__ int tile_at(int b, int G, int T, int r)
 // state (bit-identical to the sweeps' own evaluation) on one tile, for every
 // field of the cube whose search is still running; LDS histograms flushed
 // with integer atomics.
-template <typename DT>
+template <typename DT, int S>
 __device__ void tile_histogram(const4<CubeArgs<DT>> &a, int i0, int j0, int kb, int ke, float *smem)
 {
+    GEO_TILE_GEOMETRY(S);
     const DevScalars *sc = a.c.sc;
     uint32_t *hc = reinterpret_cast<uint32_t *>(smem);                              // [2][2048]
     unsigned long long *hm = reinterpret_cast<unsigned long long *>(smem + 2 * kHistBins);  // [2][2048]
@@ -168,9 +183,10 @@ __device__ __forceinline__ void block_sum8(double (&x)[8], double *red /* 8 * NT
         }
 }
 
-template <typename DT>
+template <typename DT, int S>
 __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape sh)
 {
+    GEO_TILE_GEOMETRY(S);
     using P = typename PairOf<DT>::type;
     // [band parity][y1v, y1h, y2v, y2h] masked | u' by band parity |
     // w1', w2' planes read by neighbours (ud_h, lr_v, c_v, c_h)
@@ -183,15 +199,16 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
     __shared__ int tile0[kMaxBatch + 1];
     static_assert(sizeof(smem) >= 2 * kHistBins * 12, "LDS holds the search histograms");
 
-    // The tiles of the cubes that work in this slot, one cube after another:
-    // a cube that idles takes none, so the persistent blocks, and the XCDs,
-    // share the working cubes' tiles evenly (with the full list, a batch in
-    // which a few cubes still run would leave most blocks without work).
-    // Every block reads the same flags, written before this launch.
+    // The tiles of the cubes of this tile shape that work in this slot, one
+    // cube after another: a cube that idles takes none, so the persistent
+    // blocks, and the XCDs, share the working cubes' tiles evenly (with the
+    // full list, a batch in which a few cubes still run would leave most
+    // blocks without work). Every block reads the same flags, written before
+    // this launch.
     static_assert(kMaxBatch <= 64, "one wavefront scans the cubes");
     if (threadIdx.x < 64) {
         const int c = threadIdx.x;
-        int x = c < sh.ncubes && !idle(cubes[c].c.sc) ? cubes[c].c.ntiles : 0;
+        int x = c < sh.ncubes && cubes[c].c.g.shape == S && !idle(cubes[c].c.sc) ? cubes[c].c.ntiles : 0;
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
             const int y = __shfl_up(x, o, 64);
@@ -220,7 +237,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
     for (int r = 0;; ++r) {
         // (the working cubes' tile count is read from LDS at each tile rather
         // than kept live through the march)
-        const int t = tile_at(blockIdx.x, sh.grid_a, tile0[sh.ncubes], r);
+        const int t = tile_at(blockIdx.x, sh.shape_grid[S], tile0[sh.ncubes], r);
         if (t < 0) break;
         int cube = 0;
         while (tile0[cube + 1] <= t) ++cube;
@@ -230,7 +247,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
         const4<CubeArgs<DT>> &a = ((const4<CubeArgs<DT>> *)cubes)[cube];
         DevScalars *sc = a.c.sc;
         if (idle(sc)) continue;  // never taken: an idle cube has no tiles in the list
-        const SweepGrid g{a.c.g.tj, a.c.g.ti, a.c.g.tk, a.c.g.kc};
+        const SweepGrid g{a.c.g.tj, a.c.g.ti, a.c.g.tk, a.c.g.kc, S};
         const int tj = lt % g.tj, rest = lt / g.tj;
         const int j0 = tj * TJ, i0 = (rest % g.ti) * TI, kb = (rest / g.ti) * g.kc;
         const Dims d = load_dims(a.c.d);
@@ -243,7 +260,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
         // completes the iteration once both levels are final.
         if (!(sc->sel[0].done && sc->sel[1].done)) {
             if (tid == 0) sc->hist_slot = 1u;
-            tile_histogram<DT>(a, i0, j0, kb, ke, smem);
+            tile_histogram<DT, S>(a, i0, j0, kb, ke, smem);
             continue;
         }
         if (tid == 0) sc->hist_slot = 0u;
@@ -948,14 +965,20 @@ int resident_grid()
 {
     // computed once per process (thread-safe initialisation of a local static)
     static const int cached = [] {
-        int dev = 0, cus = 256, per = 2;
+        int dev = 0, cus = 256, p0 = 1, p1 = 1;
         if (hipGetDevice(&dev) == hipSuccess) {
             hipDeviceProp_t prop;
             if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
         }
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_sweep_a<DT>, NT, 0) != hipSuccess || per < 1)
-            per = 1;
-        return cus * per;
+        // the smaller occupancy of the tile shapes in use
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p0, k_sweep_a<DT, 0>, NT, 0) != hipSuccess || p0 < 1)
+            p0 = 1;
+        p1 = p0;
+        if constexpr (sizeof(DT) == 4)
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&p1, k_sweep_a<DT, 1>, NT, 0) != hipSuccess ||
+                p1 < 1)
+                p1 = 1;
+        return cus * (p0 < p1 ? p0 : p1);
     }();
     return cached;
 }
@@ -976,7 +999,9 @@ void cube_entry_t(CubeArgs<DT> *a, const Dims &d, const float *v, void *ws, cons
     c.hist = (Hist *)(b + L.hist);
     c.cand = (float *)(b + L.cand);
     c.ccount = (uint32_t *)(b + L.ccount);
-    c.g = sweep_grid(d.n1, d.n2, d.n3, band_chunk(d.n1, d.n2, d.n3, kc, sweep_a_grid(sizeof(DT), 1 << 30)));
+    const int shape = tile_shape(d.n1, d.n2, (int)sizeof(DT));
+    c.g = sweep_grid(d.n1, d.n2, d.n3, band_chunk(d.n1, d.n2, d.n3, kc, sweep_a_grid(sizeof(DT), 1 << 30), shape),
+                     shape);
     c.ntiles = c.g.blocks();
     c.capt = (int)(L.cap / c.ntiles);
     c.tile0 = tile0;
@@ -1014,7 +1039,13 @@ hipError_t slot_t(const void *table, const LaunchShape &sh, hipStream_t st, hipE
     const CubeArgs<DT> *cubes = (const CubeArgs<DT> *)table;
     const int stride = (int)sizeof(CubeArgs<DT>);
     if (nev >= 2) (void)hipEventRecord(ev[0], st);
-    hipLaunchKernelGGL(k_sweep_a<DT>, dim3(sh.grid_a), dim3(NT), 0, st, cubes, sh);
+    // one persistent launch per tile shape present (each takes the tiles of
+    // its cubes)
+    if (sh.shape_tiles[0] > 0)
+        hipLaunchKernelGGL((k_sweep_a<DT, 0>), dim3(sh.shape_grid[0]), dim3(NT), 0, st, cubes, sh);
+    if constexpr (sizeof(DT) == 4)  // BF16 duals use 8 x 128 tiles only
+        if (sh.shape_tiles[1] > 0)
+            hipLaunchKernelGGL((k_sweep_a<DT, 1>), dim3(sh.shape_grid[1]), dim3(NT), 0, st, cubes, sh);
     if (nev >= 2) (void)hipEventRecord(ev[1], st);
     hipError_t e = launch_select_window(table, stride, sh.ncubes, kPrefetchBlocks, st);
     if (e != hipSuccess) return e;

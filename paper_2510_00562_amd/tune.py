@@ -35,7 +35,7 @@ def model_candidates(dims, dual_storage=0, n=4, c0=2.0, lo=8, hi=64):
     for kc in range(lo, hi + 1):
         costs, key = [], []
         for d in dims:
-            used, tiles, _, _ = geo_sweep_geometry(d, kc)
+            used, tiles, _, _ = geo_sweep_geometry(d, kc, dual_storage=dual_storage)
             chunks = -(-d.n3 // used)
             bands = np.minimum(used, d.n3 - used * np.arange(chunks))
             # tile order within a cube: pixel tiles fastest, band chunks slowest

@@ -66,10 +66,11 @@ def test_sweep_geometry_is_host_side():
     assert geo.geo_sweep_geometry(geo.dims_of((360, 100, 100)), 3)[:2] == (8, 13 * 1 * 45)
     L = geo.lib()
     x = ctypes.c_int32()
-    assert L.geo_sweep_geometry(geo.geo_dims(0, 4, 4), 8, 256, *[ctypes.byref(x)] * 4) == -1
-    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), -1, 256, *[ctypes.byref(x)] * 4) == -1
-    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 0, 0, *[ctypes.byref(x)] * 4) == -1
-    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 8, 256, None, *[ctypes.byref(x)] * 3) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(0, 4, 4), 0, 8, 256, *[ctypes.byref(x)] * 4) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 5, 8, 256, *[ctypes.byref(x)] * 4) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 0, -1, 256, *[ctypes.byref(x)] * 4) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 0, 0, 0, *[ctypes.byref(x)] * 4) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 0, 8, 256, None, *[ctypes.byref(x)] * 3) == -1
     assert L.geo_sweep_blocks(7, ctypes.byref(x)) == -1
     assert L.geo_sweep_blocks(0, None) == -1
 
@@ -111,3 +112,31 @@ def test_default_band_chunk_balances_the_blocks(shape, blocks, chunk):
         if u == kc:  # a raised chunk repeats a deeper one
             cost[kc] = -(-tiles // min(blocks, tiles)) * (min(kc, shape[0]) + 2)
     assert used == min(cost, key=lambda kc: (cost[kc], -kc))
+
+
+@pytest.mark.parametrize("shape, rows_cols", [
+    # (N3, N1, N2): a width of 160 fills two 128-wide tiles to 62.5% and
+    # three 64-wide ones to 83%: 16 x 64 tiles
+    ((111, 160, 160), (16, 64)),
+    # widths that 128-wide tiles fill as well as 64-wide ones keep 8 x 128
+    ((128, 256, 256), (8, 128)),
+    ((111, 128, 100), (8, 128)),
+    ((198, 120, 120), (8, 128)),
+    # 64 columns fill one 64-wide tile, half a 128-wide one
+    ((16, 64, 64), (16, 64)),
+    # 16-row tiles would leave half the rows of an 8-row cube empty
+    ((5, 8, 100), (8, 128)),
+    # 190 columns: 74% of two 128-wide tiles, 99% of three 64-wide ones
+    ((50, 96, 190), (16, 64)),
+])
+def test_tile_shape_follows_the_fill(shape, rows_cols):
+    """A cube gets 16 x 64 tiles when their share of points inside the cube
+    beats that of 8 x 128 tiles by more than 3%; with BF16 duals always
+    8 x 128. The tile count follows the shape."""
+    import paper_2510_00562_amd as geo
+    n3, n1, n2 = shape
+    d = geo.dims_of(shape)
+    kc, tiles, ti, tj = geo.geo_sweep_geometry(d, 16)
+    assert (ti, tj) == rows_cols
+    assert tiles == -(-n1 // ti) * -(-n2 // tj) * -(-n3 // kc)
+    assert geo.geo_sweep_geometry(d, 16, dual_storage=geo.GEO_STORE_BF16)[2:] == (8, 128)
