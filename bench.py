@@ -277,7 +277,7 @@ def bench_batch(args):
         wss.append(geo.Workspace(geo.geo_workspace_size(d, p)))
     total = sum(v.numel() for v in vs)
     table = geo.Workspace(geo.geo_batch_table_size(len(vs)))
-    kc, tune_ms = tune_band_chunk(dims, ps, vs, wss, table, candidates=(16, 24, 32))
+    kc, tune_ms = tune_band_chunk(dims, ps, vs, wss, table, candidates="auto")
     K, W = args.steps, args.warmup
 
     # per-cube loop: each cube alone, one after the other, at the band chunk

@@ -15,6 +15,27 @@ from . import geo_batch_step, geo_state_init, geo_sweep_blocks, geo_sweep_geomet
 CANDIDATES = (16, 32, 64)
 
 
+def _busiest_block(cost, G):
+    """Longest per-block total when G persistent blocks take the tiles of
+    `cost` (in the sweep's order) as the sweep hands them out: each of the 8
+    XCDs a contiguous eighth of the list, its blocks every (G/8)-th tile."""
+    import numpy as np
+    T = cost.size
+    if T == 0:
+        return 0.0
+    g = min(G, T)
+    if g >= 8 and g % 8 == 0:
+        per = g // 8
+        load = np.zeros(g)
+        for x in range(8):
+            seg = cost[x * T // 8:(x + 1) * T // 8]
+            load[x + 8 * np.arange(per)] = np.bincount(np.arange(seg.size) % per, weights=seg,
+                                                       minlength=per)
+    else:
+        load = np.bincount(np.arange(T) % g, weights=cost, minlength=g)
+    return float(load.max())
+
+
 def model_candidates(dims, dual_storage=0, n=4, c0=2.0, lo=8, hi=64):
     """The n band chunks in [lo, hi] that a load-balance model of the
     persistent sweep ranks fastest for these cubes.
@@ -22,42 +43,30 @@ def model_candidates(dims, dual_storage=0, n=4, c0=2.0, lo=8, hi=64):
     A tile costs its bands plus c0 band-equivalents of fixed work (its halo
     band, the pipeline fill, its partial sums). The model lays the tiles of
     the cubes out in the sweep's order, hands them to the G persistent
-    blocks as the sweep does (each of the 8 XCDs a contiguous eighth of the
-    list, its blocks taking every (G/8)-th tile of it), and takes the
-    busiest block's total as the sweep's length. Deep chunks leave blocks
-    idle when there are few tiles, shallow ones pay the fixed work more
-    often, and a tile count just past a multiple of G costs almost a whole
-    extra round. Chunks that cut every cube into the same number of chunks
-    are one candidate (the smallest, whose chunks are the most even)."""
+    blocks as the sweep does, and takes the busiest block's total as the
+    sweep's length; cubes of the two tile shapes run in two launches one
+    after the other, so their lengths add. Deep chunks leave blocks idle
+    when there are few tiles, shallow ones pay the fixed work more often,
+    and a tile count just past a multiple of G costs almost a whole extra
+    round. Chunks that cut every cube into the same number of chunks are one
+    candidate (the smallest, whose chunks are the most even)."""
     import numpy as np
     G = geo_sweep_blocks(dual_storage)
     est, seen = {}, set()
     for kc in range(lo, hi + 1):
-        costs, key = [], []
+        costs, key = {}, []
         for d in dims:
-            used, tiles, _, _ = geo_sweep_geometry(d, kc, dual_storage=dual_storage)
+            used, tiles, rows, _ = geo_sweep_geometry(d, kc, dual_storage=dual_storage)
             chunks = -(-d.n3 // used)
             bands = np.minimum(used, d.n3 - used * np.arange(chunks))
             # tile order within a cube: pixel tiles fastest, band chunks slowest
-            costs.append(np.repeat(bands + c0, tiles // chunks))
+            costs.setdefault(rows, []).append(np.repeat(bands + c0, tiles // chunks))
             key.append(chunks)
         key = tuple(key)
         if key in seen:
             continue
         seen.add(key)
-        cost = np.concatenate(costs)
-        T = cost.size
-        g = min(G, T)
-        load = np.zeros(g)
-        if g >= 8 and g % 8 == 0:
-            per = g // 8
-            for x in range(8):
-                seg = cost[x * T // 8:(x + 1) * T // 8]
-                idx = np.arange(seg.size) % per
-                load[x + 8 * np.arange(per)] = np.bincount(idx, weights=seg, minlength=per)
-        else:
-            load = np.bincount(np.arange(T) % g, weights=cost, minlength=g)
-        est[kc] = float(load.max())
+        est[kc] = sum(_busiest_block(np.concatenate(c), G) for c in costs.values())
     return sorted(est, key=est.get)[:n]
 
 
