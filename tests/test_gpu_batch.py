@@ -147,13 +147,16 @@ def test_band_chunk_raised_at_the_tile_limit():
 
 
 def test_working_cubes_share_the_persistent_blocks():
-    """Three cubes of 128 tiles each (8-band tiles): more tiles than resident
-    sweep A blocks, so the blocks take XCD-ordered tile ranges. One cube meets
-    its stopping rule early; from then on only the other two cubes' tiles are
-    in the list the blocks share. Every cube's iterates, iteration count and
-    stopping flag must still be those of the cube run alone."""
-    shapes = [(64, 64, 256), (64, 64, 250), (64, 60, 256)]
-    tols = [3e-3, 0.0, 0.0]
+    """Three cubes of 128 tiles each (8 x 128 pixels, 8 bands) and one of
+    240 (16 x 64 pixels: its width of 160 fills 64-wide tiles better): more
+    tiles than resident sweep A blocks in the 8 x 128 launch, so the blocks
+    take XCD-ordered tile ranges, and a second launch for the 16 x 64 cube.
+    One cube meets its stopping rule early; from then on only the other
+    cubes' tiles are in the list the blocks share. Every cube's iterates,
+    iteration count and stopping flag must still be those of the cube run
+    alone."""
+    shapes = [(64, 64, 256), (64, 64, 250), (64, 60, 256), (64, 160, 160)]
+    tols = [3e-3, 0.0, 0.0, 0.0]
     n_iter = 80
     announce(f"batch {shapes}, tolerances {tols}, {n_iter} iterations, 8-band tiles")
     torch_cuda()
@@ -165,7 +168,8 @@ def test_working_cubes_share_the_persistent_blocks():
                                  [x[3] for x in st], table, n_iter, use_graph=True)
     states = [get_state(geo, d, p, ws, vd, c["v"].shape) for (d, p, vd, ws), c in zip(st, cs)]
     assert res[0].converged and res[0].iters < n_iter - 20, res[0].iters  # stops near 37
-    assert [r.iters for r in res[1:]] == [n_iter, n_iter]
+    assert [r.iters for r in res[1:]] == [n_iter] * 3
+    assert [geo.geo_sweep_geometry(d, 8)[2:] for d, _, _, _ in st] == [(8, 128)] * 3 + [(16, 64)]
     for c, tol, r, s in zip(cs, tols, res, states):
         r1, s1 = run_solo(geo, c, n_iter, tol=tol, band_chunk=8)
         assert r.iters == r1.iters and r.converged == r1.converged
