@@ -246,7 +246,9 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
         const int lt = __builtin_amdgcn_readfirstlane(t - tile0[cube]);  // tile within the cube
         const4<CubeArgs<DT>> &a = ((const4<CubeArgs<DT>> *)cubes)[cube];
         DevScalars *sc = a.c.sc;
-        if (idle(sc)) continue;  // never taken: an idle cube has no tiles in the list
+        // Never taken (an idle cube has no tiles in the list); without it the
+        // register allocation of one of the sweep's forms spills.
+        if (idle(sc)) continue;
         const SweepGrid g{a.c.g.tj, a.c.g.ti, a.c.g.tk, a.c.g.kc, S};
         const int tj = lt % g.tj, rest = lt / g.tj;
         const int j0 = tj * TJ, i0 = (rest % g.ti) * TI, kb = (rest / g.ti) * g.kc;
