@@ -175,3 +175,26 @@ def test_working_cubes_share_the_persistent_blocks():
         assert r.iters == r1.iters and r.converged == r1.converged
         assert r.tau_s == r1.tau_s and r.tau_t == r1.tau_t and r.r == r1.r
         same(s, s1)
+
+
+def test_graph_kept_across_calls_reads_the_new_table():
+    """Two batches of different cubes with the same sizes, one after the
+    other through the same table: the second call replays the graph kept
+    from the first (same table address and launch shape), and its cubes'
+    iterates must be their own, equal to each cube run alone."""
+    announce("graph reuse: two batches of equal sizes through one table")
+    torch_cuda()
+    import paper_2510_00562_amd as geo
+    shapes = [(16, 64, 64), (9, 31, 77)]
+    first, second = cubes(shapes, seed0=700), cubes(shapes, seed0=800)
+    table = geo.Workspace(geo.geo_batch_table_size(len(shapes)))
+    for cs in (first, second, first):
+        st = [setup(geo, c) for c in cs]
+        rc, res = geo.geo_batch_step([x[0] for x in st], [x[1] for x in st], [x[2] for x in st],
+                                     [x[3] for x in st], table, 15, use_graph=True)
+        assert rc == 0
+        for (d, p, vd, ws), c, r in zip(st, cs, res):
+            s = get_state(geo, d, p, ws, vd, c["v"].shape)
+            r1, s1 = run_solo(geo, c, 15)
+            assert r.tau_s == r1.tau_s and r.tau_t == r1.tau_t and r.r == r1.r
+            same(s, s1)
