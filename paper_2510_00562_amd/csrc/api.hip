@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <memory>
+#include <type_traits>
 #include <mutex>
 #include <vector>
 
@@ -68,33 +70,41 @@ thread_local hipError_t g_last_hip = hipSuccess;
 // graph captured for the same device, table address, storage and shape is
 // the same graph. A request loop that keeps its batch for several rounds
 // then pays the capture and instantiation once. At most kGraphCache graphs
-// are kept (the oldest is destroyed); they live until the process ends.
+// are kept (the oldest leaves first); a graph is destroyed when it has left
+// the cache and no call still replays it.
 struct GraphKey {
     int device;
     int dual_bytes;
     const void *table;
     LaunchShape sh;
 };
+using GraphRef = std::shared_ptr<std::remove_pointer<hipGraphExec_t>::type>;
 constexpr size_t kGraphCache = 16;
 std::mutex g_graph_mu;
-std::vector<std::pair<GraphKey, hipGraphExec_t>> g_graphs;
+// never destroyed: the graphs still cached at exit are left to the runtime's
+// own teardown rather than destroyed after it
+std::vector<std::pair<GraphKey, GraphRef>> &graph_cache()
+{
+    static auto *v = new std::vector<std::pair<GraphKey, GraphRef>>();
+    return *v;
+}
 
-hipGraphExec_t cached_graph(const GraphKey &k)
+GraphRef cached_graph(const GraphKey &k)
 {
     std::lock_guard<std::mutex> lock(g_graph_mu);
-    for (auto &e : g_graphs)
+    for (auto &e : graph_cache())
         if (memcmp(&e.first, &k, sizeof k) == 0) return e.second;
     return nullptr;
 }
 
-void keep_graph(const GraphKey &k, hipGraphExec_t g)
+GraphRef keep_graph(const GraphKey &k, hipGraphExec_t g)
 {
+    GraphRef ref(g, [](hipGraphExec_t x) { (void)hipGraphExecDestroy(x); });
     std::lock_guard<std::mutex> lock(g_graph_mu);
-    if (g_graphs.size() >= kGraphCache) {
-        (void)hipGraphExecDestroy(g_graphs.front().second);
-        g_graphs.erase(g_graphs.begin());
-    }
-    g_graphs.emplace_back(k, g);
+    auto &c = graph_cache();
+    if (c.size() >= kGraphCache) c.erase(c.begin());
+    c.emplace_back(k, ref);
+    return ref;
 }
 
 int hip_status(hipError_t e)
@@ -247,6 +257,7 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
     const int every = p[0].check_every > 0 ? p[0].check_every : 32;
 
     hipGraphExec_t gexec = nullptr;
+    GraphRef gref;  // keeps the graph alive while this call replays it
     hipGraph_t graph = nullptr;
     GraphKey gkey;
     memset(&gkey, 0, sizeof gkey);  // compared bytewise, padding included
@@ -255,7 +266,8 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         gkey.table = table;
         gkey.sh = sh;
         rc = hip_status(hipGetDevice(&gkey.device));
-        if (!rc) gexec = cached_graph(gkey);
+        if (!rc) gref = cached_graph(gkey);
+        gexec = gref.get();
     }
     const bool new_graph = use_graph && !phase_ms && !rc && !gexec;
     if (new_graph) {
@@ -273,7 +285,7 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         if (cs) (void)hipStreamDestroy(cs);
         if (graph) (void)hipGraphDestroy(graph);  // the instantiated graph is independent of it
         graph = nullptr;
-        if (!rc) keep_graph(gkey, gexec);
+        if (!rc) gref = keep_graph(gkey, gexec);
         else if (gexec) {
             (void)hipGraphExecDestroy(gexec);
             gexec = nullptr;
