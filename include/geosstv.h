@@ -162,8 +162,11 @@ int geo_solve(geo_dims dims, const geo_params *p, const float *v,
  *       ws[c] are device pointers); every p[c].dual_storage must be equal.
  *   table: device buffer of geo_batch_table_size bytes (256-byte aligned)
  *       for the launch table; it may be reused by later calls.
- *   use_graph != 0: one iteration's launch sequence is captured once into a
- *       HIP graph and replayed (fewer launches on the host).
+ *   use_graph != 0: one iteration's launch sequence is captured into a HIP
+ *       graph and replayed (fewer launches on the host). The instantiated
+ *       graph is kept (up to 16 per process) and replayed by later calls on
+ *       the same device with the same table address, storage and cube
+ *       sizes; the table's contents are uploaded by every call.
  * Blocking; returns GEO_ENONFINITE if any cube saw NaN/Inf, else GEO_MAXITER
  * if any cube with tol > 0 did not meet its rule, else GEO_OK. 1 <= n_cubes
  * <= 64. */
