@@ -73,6 +73,9 @@ def test_sweep_geometry_is_host_side():
     assert L.geo_sweep_geometry(geo.geo_dims(4, 4, 4), 0, 8, 256, None, *[ctypes.byref(x)] * 3) == -1
     assert L.geo_sweep_blocks(7, ctypes.byref(x)) == -1
     assert L.geo_sweep_blocks(0, None) == -1
+    import torch
+    if not torch.cuda.is_available():  # no device: the block count is a device query
+        assert L.geo_sweep_blocks(0, ctypes.byref(x)) == -3
 
 
 @pytest.mark.parametrize("shape, blocks, chunk", [
