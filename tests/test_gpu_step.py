@@ -55,8 +55,11 @@ def problem(shape, seed):
     return c
 
 
+# (N3, N1, N2). 8 x 128 tiles: (5, 13, 70), (1, 1, 1), (3, 1, 5), (2, 7, 1);
+# 16 x 64 tiles: (17, 9, 130), (33, 20, 64), (16, 64, 64), and (12, 40, 150),
+# whose 3 x 3 pixel tiles per band chunk give one tile neighbours on all sides.
 @pytest.mark.parametrize("shape", [(5, 13, 70), (17, 9, 130), (1, 1, 1), (3, 1, 5), (2, 7, 1),
-                                   (33, 20, 64), (16, 64, 64)])
+                                   (33, 20, 64), (16, 64, 64), (12, 40, 150)])
 def test_one_step_from_random_state(ora, shape):
     announce(f"one step random state {shape}")
     c = problem(shape, 3)
@@ -78,7 +81,7 @@ def test_one_step_from_random_state(ora, shape):
     assert ts > 0 and tt > 0 and r > prm["eps"]
 
 
-@pytest.mark.parametrize("shape", [(5, 13, 70), (17, 9, 130)])
+@pytest.mark.parametrize("shape", [(5, 13, 70), (17, 9, 130), (12, 40, 150)])
 def test_few_steps_from_initial_point(ora, shape):
     announce(f"10 steps from init {shape}")
     c = problem(shape, 4)
