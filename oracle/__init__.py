@@ -5,7 +5,8 @@ of the benchmark may import this package. The GPU product path shares no code
 with it and never calls it.
 
 A ctypes wrapper around ``geosstv_oracle.c`` (plain double-precision loops,
-one per operator, the steps of Alg. 1 in the paper's order). Arrays are numpy
+one per operator; the generic P-PDS update of eq. (7) applied to problem (20)
+block by block). Arrays are numpy
 float64 in band-sequential layout: shape (N3, N1, N2), element (i, j, k) at
 [k, i, j]. Multi-plane fields carry a leading plane axis: D x and the duals
 y1, y2 have 2 planes (vertical, horizontal); L y and w1, w2 have 6 planes
@@ -23,7 +24,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "geosstv_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-# Step sizes printed after eq. (24) of the paper, in the order of Alg. 1.
+# Step sizes printed after eq. (24) of the paper.
 STEP_U, STEP_W1, STEP_W2, STEP_S, STEP_T, STEP_Y = 1 / 13, 1 / 4, 1 / 4, 1.0, 1 / 3, 1 / 5
 
 
@@ -208,7 +209,8 @@ PLANES = dict(u=1, s=1, t=1, w1=6, w2=6, y1=2, y2=2, y3=1, y4=1)
 
 
 class Solver:
-    """Alg. 1 for problem (20) on one cube, in double precision."""
+    """P-PDS (eq. (7), the iteration of Alg. 1) for problem (20) on one cube,
+    in double precision."""
 
     def __init__(self, v, eps, alpha, beta, mu_lo=0.0, mu_hi=1.0, omega=0.03, state=None):
         self.v = _c(v)

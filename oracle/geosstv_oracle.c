@@ -8,7 +8,8 @@
  * shares no code with it and never calls it.
  *
  * Plain, slow and obviously correct on purpose: one loop per operator, the
- * steps of Alg. 1 in the paper's order, double precision throughout, no
+ * generic P-PDS update (eq. (7)) applied to problem (20) block by block (the
+ * same iteration that Alg. 1 spells out), double precision throughout, no
  * fusion and no blocking. OpenMP only splits the outer loop of each sweep.
  *
  * Cube layout: band-sequential, element (i, j, k) of the N1 x N2 x N3 cube
@@ -30,7 +31,8 @@
  *    edges only, so their entries on the last row (vertical field) and last
  *    column (horizontal field) are masked to zero on input, and the ud and lr
  *    grids likewise hold only interior edges.
- *  - Initial point of Alg. 1: u = v, every other variable zero.
+ *  - Initial point: u = v, every other variable zero.
+ *  - Dual step of eq. (7) taken with "+ Sigma K x'", as Alg. 1 has it.
  *  - l1-ball projection (cited fast algorithm): any exact Euclidean
  *    projection; here Michelot's active-set iteration.
  */
@@ -383,7 +385,7 @@ void ora_prox_l12(const double *xa, const double *xb, ix n, double gamma, double
     }
 }
 
-/* ----------------------------- Algorithm 1 ------------------------------ */
+/* --------------- P-PDS (eq. (7)) applied to problem (20) --------------- */
 
 typedef struct {
     double eps, alpha, beta; /* radii of (18), (16), (17)              */
@@ -391,7 +393,9 @@ typedef struct {
     double omega;            /* balance of GeoSSTV, eq. (13)             */
 } ora_params;
 
-/* Step sizes printed after eq. (24). */
+/* Step sizes printed after eq. (24): the primal ones form the diagonal
+ * preconditioner T = diag(G_U, G_S, G_T, G_W1, G_W2), the dual one Sigma =
+ * G_Y I for all four dual blocks. */
 static const double G_U = 1.0 / 13.0, G_W1 = 0.25, G_W2 = 0.25, G_S = 1.0,
                     G_T = 1.0 / 3.0, G_Y = 0.2;
 
@@ -421,120 +425,176 @@ void ora_init(int n1, int n2, int n3, const double *v, double *u, double *s, dou
     memset(y4, 0, sizeof(double) * N);
 }
 
-/* number of doubles of scratch that one step needs, in units of N */
-#define STEP_WS 46
+/* Problem (20) in the form of problem (6): five primal blocks
+ * x = (u, s, t, w1, w2) with
+ *   f(x) = iota_R(u) + iota_{B1,alpha}(s) + iota_{B1,beta}(t)
+ *          + omega ||w1||_{1,2} + ||w2||_{1,2},
+ * four dual blocks z = K x with
+ *   K x = ( D u - L^T w1,  D D_s u - L^T w2,  D_v t,  u + s + t ),
+ * and g(z) = iota_{0}(z1) + iota_{0}(z2) + iota_{0}(z3) + iota_{B2,eps}^v(z4). */
+typedef struct { double *u, *s, *t, *w1, *w2; } primal; /* 1+1+1+6+6 planes */
+typedef struct { double *y1, *y2, *y3, *y4; } dual;     /* 2+2+1+1 planes   */
 
-static void step_ws(int n1, int n2, int n3, const ora_params *p, const double *v,
-                    double *u, double *s, double *t, double *w1, double *w2,
-                    double *y1, double *y2, double *y3, double *y4, double *trace, double *ws)
+/* out = K x. tmp holds 6N doubles. */
+static void apply_k(int n1, int n2, int n3, const primal *x, const dual *out, double *tmp)
 {
     ix N = (ix)n1 * n2 * n3;
-    double *a = ws, *b = a + N, *c2 = b + N, *c6 = c2 + 2 * N, *un = c6 + 6 * N;
-    double *sn = un + N, *tn = sn + N, *w1n = tn + N, *w2n = w1n + 6 * N, *up = w2n + 6 * N;
-    double *sp = up + N, *tp = sp + N, *w1p = tp + N, *w2p = w1p + 6 * N;
-    double *t1 = w2p + 6 * N, *t2 = t1 + 2 * N; /* operator temporaries, 2N each */
+    double *a = tmp, *b = tmp + 2 * N, *c = tmp + 4 * N;
+    /* first row: D u - L^T w1 */
+    ora_d(n1, n2, n3, x->u, out->y1);
+    l_t_ws(n1, n2, n3, x->w1, a, b, c);
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < 2 * N; ++q) out->y1[q] -= a[q];
+    /* second row: D (D_s u) - L^T w2 */
+    ora_ds(n1, n2, n3, x->u, c);
+    ora_d(n1, n2, n3, c, out->y2);
+    l_t_ws(n1, n2, n3, x->w2, a, b, c);
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < 2 * N; ++q) out->y2[q] -= a[q];
+    /* third row: D_v t */
+    ora_dv(n1, n2, n3, x->t, out->y3);
+    /* fourth row: u + s + t */
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) out->y4[q] = x->u[q] + x->s[q] + x->t[q];
+}
 
-    /* step 1: u+ = P_R(u - g_u (D^T y1 + D_s^T D^T y2 + y4)) */
-    d_t_ws(n1, n2, n3, y1, a, t1);
-    d_t_ws(n1, n2, n3, y2, b, t1);
-    ora_ds_t(n1, n2, n3, b, up); /* up used as scratch here */
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < N; ++q) a[q] = u[q] - G_U * (a[q] + up[q] + y4[q]);
-    ora_proj_box(a, N, p->mu_lo, p->mu_hi, un);
-
-    /* step 2: s+ = P_{B1,alpha}(s - g_s y4) */
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < N; ++q) a[q] = s[q] - G_S * y4[q];
-    double tau_s = ora_proj_l1(a, N, p->alpha, sn);
-
-    /* step 3: t+ = P_{B1,beta}(t - g_t (D_v^T y3 + y4)) */
-    ora_dv_t(n1, n2, n3, y3, a);
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < N; ++q) a[q] = t[q] - G_T * (a[q] + y4[q]);
-    double tau_t = ora_proj_l1(a, N, p->beta, tn);
-
-    /* step 4: w1+ = prox_{g_w1 omega ||.||_{1,2}}(w1 + g_w1 L y1) */
-    ora_l(n1, n2, n3, y1, c6);
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < 6 * N; ++q) c6[q] = w1[q] + G_W1 * c6[q];
-    for (int g = 0; g < 3; ++g)
-        ora_prox_l12(c6 + 2 * g * N, c6 + (2 * g + 1) * N, N, G_W1 * p->omega,
-                     w1n + 2 * g * N, w1n + (2 * g + 1) * N);
-
-    /* step 5: w2+ = prox_{g_w2 ||.||_{1,2}}(w2 + g_w2 L y2) */
-    ora_l(n1, n2, n3, y2, c6);
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < 6 * N; ++q) c6[q] = w2[q] + G_W2 * c6[q];
-    for (int g = 0; g < 3; ++g)
-        ora_prox_l12(c6 + 2 * g * N, c6 + (2 * g + 1) * N, N, G_W2,
-                     w2n + 2 * g * N, w2n + (2 * g + 1) * N);
-
-    /* steps 6-10: extrapolation x' = 2 x+ - x */
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < N; ++q) {
-        up[q] = 2.0 * un[q] - u[q];
-        sp[q] = 2.0 * sn[q] - s[q];
-        tp[q] = 2.0 * tn[q] - t[q];
-    }
-    #pragma omp parallel for schedule(static)
+/* out = K^T y, column by column of K. tmp holds 6N doubles. */
+static void apply_kt(int n1, int n2, int n3, const dual *y, const primal *out, double *tmp)
+{
+    ix N = (ix)n1 * n2 * n3;
+    double *a = tmp, *b = tmp + 2 * N, *c = tmp + 4 * N;
+    /* u column: D^T y1 + D_s^T (D^T y2) + y4 */
+    d_t_ws(n1, n2, n3, y->y1, out->u, a);
+    d_t_ws(n1, n2, n3, y->y2, b, a);
+    ora_ds_t(n1, n2, n3, b, c);
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) out->u[q] = out->u[q] + c[q] + y->y4[q];
+    /* s column: y4 */
+    memcpy(out->s, y->y4, sizeof(double) * N);
+    /* t column: D_v^T y3 + y4 */
+    ora_dv_t(n1, n2, n3, y->y3, out->t);
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) out->t[q] += y->y4[q];
+    /* w1 and w2 columns: -L y1 and -L y2 */
+    ora_l(n1, n2, n3, y->y1, out->w1);
+    ora_l(n1, n2, n3, y->y2, out->w2);
+#pragma omp parallel for schedule(static)
     for (ix q = 0; q < 6 * N; ++q) {
-        w1p[q] = 2.0 * w1n[q] - w1[q];
-        w2p[q] = 2.0 * w2n[q] - w2[q];
+        out->w1[q] = -out->w1[q];
+        out->w2[q] = -out->w2[q];
+    }
+}
+
+/* x <- prox_{T f}(x), block by block: the box (21), the two l1 balls
+ * (16), (17) and the group shrinks (24) with thresholds G_W1 omega and G_W2.
+ * The l1 thresholds go to tau[0] (s) and tau[1] (t). */
+static void prox_tf(int n1, int n2, int n3, const ora_params *p, const primal *x, double *tau)
+{
+    ix N = (ix)n1 * n2 * n3;
+    ora_proj_box(x->u, N, p->mu_lo, p->mu_hi, x->u);
+    tau[0] = ora_proj_l1(x->s, N, p->alpha, x->s);
+    tau[1] = ora_proj_l1(x->t, N, p->beta, x->t);
+    for (int g = 0; g < 3; ++g) {
+        ora_prox_l12(x->w1 + 2 * g * N, x->w1 + (2 * g + 1) * N, N, G_W1 * p->omega,
+                     x->w1 + 2 * g * N, x->w1 + (2 * g + 1) * N);
+        ora_prox_l12(x->w2 + 2 * g * N, x->w2 + (2 * g + 1) * N, N, G_W2,
+                     x->w2 + 2 * g * N, x->w2 + (2 * g + 1) * N);
+    }
+}
+
+/* y <- prox_{Sigma g*}(y). The conjugate's prox comes from the Moreau
+ * decomposition (3): prox_{G g*}(z) = z - G prox_{g/G}(z / G). For the three
+ * iota_{0} blocks prox_{g/G} is 0 (eq. (22)), so those blocks pass through;
+ * for the fourth it is the projection (23) onto B_{2,eps}^v. tmp holds 2N
+ * doubles. Returns the distance ||y4/G - v||_2 that the projection tests. */
+static double prox_sgstar(int n1, int n2, int n3, const ora_params *p, const double *v,
+                          const dual *y, double *tmp)
+{
+    ix N = (ix)n1 * n2 * n3;
+    double *a = tmp, *b = tmp + N;
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) a[q] = y->y4[q] / G_Y;
+    double r = ora_proj_l2(a, v, N, p->eps, b);
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) y->y4[q] = y->y4[q] - G_Y * b[q];
+    return r;
+}
+
+/* number of doubles of scratch that one iteration needs, in units of N */
+#define STEP_WS 42
+
+/* One P-PDS iteration, eq. (7), with T and Sigma above and the dual update
+ * written with "+ Sigma K x'" as Alg. 1 has it:
+ *   x+ = prox_{T f}(x - T K^T y),   x' = 2 x+ - x,
+ *   y+ = prox_{Sigma g*}(y + Sigma K x'). */
+static void step_ws(int n1, int n2, int n3, const ora_params *p, const double *v,
+                    const primal *x, const dual *y, double *trace, double *ws)
+{
+    ix N = (ix)n1 * n2 * n3;
+    /* scratch: g (15N) holds K^T y, then x'; xn (15N) holds x+; z (6N)
+     * holds K x'; tmp (6N) is operator scratch */
+    double *g0 = ws, *xn0 = ws + 15 * N, *z0 = ws + 30 * N, *tmp = ws + 36 * N;
+    primal g = {g0, g0 + N, g0 + 2 * N, g0 + 3 * N, g0 + 9 * N};
+    primal xn = {xn0, xn0 + N, xn0 + 2 * N, xn0 + 3 * N, xn0 + 9 * N};
+    dual z = {z0, z0 + 2 * N, z0 + 4 * N, z0 + 5 * N};
+    const double step[5] = {G_U, G_S, G_T, G_W1, G_W2};
+    const ix len[5] = {N, N, N, 6 * N, 6 * N};
+    double *xb[5] = {x->u, x->s, x->t, x->w1, x->w2};
+    double *gb[5] = {g.u, g.s, g.t, g.w1, g.w2};
+    double *nb[5] = {xn.u, xn.s, xn.t, xn.w1, xn.w2};
+
+    /* primal half: forward step on each block, then the block proxes */
+    apply_kt(n1, n2, n3, y, &g, tmp);
+    for (int b = 0; b < 5; ++b) {
+        const double *xo = xb[b], *gg = gb[b];
+        double *xnew = nb[b], gam = step[b];
+#pragma omp parallel for schedule(static)
+        for (ix q = 0; q < len[b]; ++q) xnew[q] = xo[q] - gam * gg[q];
+    }
+    double tau[2];
+    prox_tf(n1, n2, n3, p, &xn, tau);
+
+    /* extrapolated point x' = 2 x+ - x, kept in g */
+    for (int b = 0; b < 5; ++b) {
+        const double *xo = xb[b], *xnew = nb[b];
+        double *xe = gb[b];
+#pragma omp parallel for schedule(static)
+        for (ix q = 0; q < len[b]; ++q) xe[q] = 2.0 * xnew[q] - xo[q];
     }
 
-    /* step 11: y1 += g_y (D u' - L^T w1') */
-    ora_d(n1, n2, n3, up, c2);
-    l_t_ws(n1, n2, n3, w1p, c6, t1, t2); /* first 2N entries of c6 as scratch */
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < 2 * N; ++q) y1[q] += G_Y * (c2[q] - c6[q]);
-
-    /* step 12: y2 += g_y (D D_s u' - L^T w2') */
-    ora_ds(n1, n2, n3, up, a);
-    ora_d(n1, n2, n3, a, c2);
-    l_t_ws(n1, n2, n3, w2p, c6, t1, t2);
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < 2 * N; ++q) y2[q] += G_Y * (c2[q] - c6[q]);
-
-    /* step 13: y3 += g_y D_v t' */
-    ora_dv(n1, n2, n3, tp, a);
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < N; ++q) y3[q] += G_Y * a[q];
-
-    /* step 14: y4' = y4 + g_y (u' + s' + t') */
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < N; ++q) y4[q] += G_Y * (up[q] + sp[q] + tp[q]);
-
-    /* step 15: y4+ = y4' - g_y P_{B2,eps}^v(y4' / g_y)  (eq. (3), (23)) */
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < N; ++q) a[q] = y4[q] / G_Y;
-    double r = ora_proj_l2(a, v, N, p->eps, b);
-    #pragma omp parallel for schedule(static)
-    for (ix q = 0; q < N; ++q) y4[q] = y4[q] - G_Y * b[q];
+    /* dual half: forward step with K x', then the conjugate proxes */
+    apply_k(n1, n2, n3, &g, &z, tmp);
+    double *yb[4] = {y->y1, y->y2, y->y3, y->y4};
+    const double *zb[4] = {z.y1, z.y2, z.y3, z.y4};
+    const ix ylen[4] = {2 * N, 2 * N, N, N};
+    for (int b = 0; b < 4; ++b) {
+        double *yy = yb[b];
+        const double *zz = zb[b];
+#pragma omp parallel for schedule(static)
+        for (ix q = 0; q < ylen[b]; ++q) yy[q] += G_Y * zz[q];
+    }
+    double r = prox_sgstar(n1, n2, n3, p, v, y, tmp);
 
     /* stopping quantity of eq. (28) */
     double dn = 0.0, un2 = 0.0;
 #pragma omp parallel for schedule(static) reduction(+ : dn, un2)
     for (ix q = 0; q < N; ++q) {
-        dn += (un[q] - u[q]) * (un[q] - u[q]);
-        un2 += u[q] * u[q];
+        dn += (xn.u[q] - x->u[q]) * (xn.u[q] - x->u[q]);
+        un2 += x->u[q] * x->u[q];
     }
     double rel = un2 > 0.0 ? sqrt(dn) / sqrt(un2) : INFINITY;
 
-    memcpy(u, un, sizeof(double) * N);
-    memcpy(s, sn, sizeof(double) * N);
-    memcpy(t, tn, sizeof(double) * N);
-    memcpy(w1, w1n, sizeof(double) * 6 * N);
-    memcpy(w2, w2n, sizeof(double) * 6 * N);
+    for (int b = 0; b < 5; ++b) memcpy(xb[b], nb[b], sizeof(double) * len[b]);
     if (trace) {
         trace[0] = rel;
         trace[1] = r;
-        trace[2] = tau_s;
-        trace[3] = tau_t;
+        trace[2] = tau[0];
+        trace[3] = tau[1];
     }
 }
 
-/* One pass of the loop body of Alg. 1 for problem (20), updating the state
- * in place. trace (may be NULL) receives
+/* One P-PDS iteration for problem (20), updating the state in place. trace
+ * (may be NULL) receives
  *   [0] ||u+ - u||_2 / ||u||_2    (stopping quantity of eq. (28); +inf when
  *                                  ||u|| = 0)
  *   [1] ||y4'/gamma - v||_2       (the distance tested in the l2 projection)
@@ -544,28 +604,33 @@ void ora_step(int n1, int n2, int n3, const ora_params *p, const double *v,
               double *u, double *s, double *t, double *w1, double *w2,
               double *y1, double *y2, double *y3, double *y4, double *trace)
 {
+    primal x = {u, s, t, w1, w2};
+    dual y = {y1, y2, y3, y4};
     double *ws = (double *)malloc(sizeof(double) * STEP_WS * (ix)n1 * n2 * n3);
-    step_ws(n1, n2, n3, p, v, u, s, t, w1, w2, y1, y2, y3, y4, trace, ws);
+    step_ws(n1, n2, n3, p, v, &x, &y, trace, ws);
     free(ws);
 }
 
-/* Run the loop of Alg. 1: at most max_iter passes, stopping after the first
- * pass whose stopping quantity (eq. (28)) is below tol (tol <= 0: run all
- * passes). done_before: passes made since the initial point by earlier
- * calls. The rule is not applied to the first pass after the initial point:
- * from u = v with zero duals that pass changes u only by the box projection,
- * so a cube already inside the box would stop there unchanged.
- * trace_all (may be NULL) gets 4 numbers per pass. Returns the pass count. */
+/* Iterate: at most max_iter iterations, stopping after the first one whose
+ * stopping quantity (eq. (28)) is below tol (tol <= 0: run all of them).
+ * done_before: iterations made since the initial point by earlier calls.
+ * The rule is not applied to the first iteration after the initial point:
+ * from u = v with zero duals that iteration changes u only by the box
+ * projection, so a cube already inside the box would stop there unchanged.
+ * trace_all (may be NULL) gets 4 numbers per iteration. Returns the
+ * iteration count. */
 int ora_run(int n1, int n2, int n3, const ora_params *p, const double *v,
             double *u, double *s, double *t, double *w1, double *w2,
             double *y1, double *y2, double *y3, double *y4,
             int max_iter, double tol, int done_before, double *trace_all)
 {
+    primal x = {u, s, t, w1, w2};
+    dual y = {y1, y2, y3, y4};
     double tr[4];
     int it = 0;
     double *ws = (double *)malloc(sizeof(double) * STEP_WS * (ix)n1 * n2 * n3);
     while (it < max_iter) {
-        step_ws(n1, n2, n3, p, v, u, s, t, w1, w2, y1, y2, y3, y4, tr, ws);
+        step_ws(n1, n2, n3, p, v, &x, &y, tr, ws);
         if (trace_all) memcpy(trace_all + 4 * it, tr, sizeof tr);
         ++it;
         if (tol > 0.0 && done_before + it >= 2 && tr[0] < tol) break;
