@@ -53,7 +53,14 @@ enum {
 enum { GEO_STORE_F32 = 0, GEO_STORE_BF16 = 1 };
 
 typedef struct {
-    int32_t n1, n2, n3; /* each >= 1; N = n1*n2*n3 < 2^31 */
+    int32_t n1, n2, n3; /* each >= 1; N = n1*n2*n3 < 2^31. The solver
+                           entry points (workspace, state, step, solve,
+                           batch, geometry) also need one band to fit the
+                           fused sweep's tile limit: at most 4096 tiles of
+                           8 x 128 and of 16 x 64 pixels per band (up to
+                           2048 x 2048 pixels); larger bands give
+                           GEO_EINVAL. The operator and projection entry
+                           points take any dims above.                     */
 } geo_dims;
 
 /* Parameters of problem (15) and of the loop of Alg. 1. The step sizes are
@@ -196,6 +203,14 @@ int geo_batch_step(int32_t n_cubes, const geo_dims *dims, const geo_params *p,
 int geo_sweep_geometry(geo_dims dims, int32_t dual_storage, int32_t requested, int32_t blocks,
                        int32_t *used_chunk, int32_t *tiles, int32_t *tile_rows,
                        int32_t *tile_cols);
+
+/* Tile capacity of a solver workspace for these dims and storage: the
+ * most tiles any band chunk that geo_sweep_geometry can report (for every
+ * request and block count) gives the cube. The per-tile regions of the
+ * workspace (partial sums, window statistics, candidate counts) hold that
+ * many tiles. Host-only; no device needed.
+ * Errors: GEO_EINVAL for bad dims, storage type or a NULL output. */
+int geo_workspace_tiles(geo_dims dims, int32_t dual_storage, int32_t *max_tiles);
 
 /* Persistent blocks of the fused sweep on the current device: a launch
  * runs min(blocks, tiles of all its cubes) blocks, and each block takes

@@ -103,6 +103,7 @@ def lib():
             "geo_batch_table_size": [i32, ctypes.POINTER(_sz)],
             "geo_sweep_geometry": [geo_dims, i32, i32, i32] + [ctypes.POINTER(i32)] * 4,
             "geo_sweep_blocks": [i32, ctypes.POINTER(i32)],
+            "geo_workspace_tiles": [geo_dims, i32, ctypes.POINTER(i32)],
             "geo_batch_step": [i32, ctypes.POINTER(geo_dims), P, ctypes.POINTER(_vp),
                                ctypes.POINTER(_vp), ctypes.POINTER(_sz), _vp, _sz, i32, i32, _vp,
                                R],
@@ -250,6 +251,14 @@ def geo_sweep_geometry(dims, requested: int = 0, blocks: int = 0,
     _check(lib().geo_sweep_geometry(dims, int(dual_storage), int(requested), int(blocks),
                                     *[ctypes.byref(x) for x in out]), "geo_sweep_geometry")
     return tuple(x.value for x in out)
+
+
+def geo_workspace_tiles(dims, dual_storage: int = GEO_STORE_F32) -> int:
+    """Tiles the per-tile regions of a solver workspace hold for these dims."""
+    n = ctypes.c_int32()
+    _check(lib().geo_workspace_tiles(dims, int(dual_storage), ctypes.byref(n)),
+           "geo_workspace_tiles")
+    return n.value
 
 
 def geo_sweep_blocks(dual_storage: int = GEO_STORE_F32) -> int:

@@ -121,6 +121,9 @@ bool dims_ok(geo_dims d)
     return N < ((int64_t)1 << 31);
 }
 
+// Cubes the solver entry points take: one band within the tile limit.
+bool solver_dims_ok(geo_dims d) { return dims_ok(d) && solver_dims_fit(d.n1, d.n2); }
+
 bool finite_nonneg(double x) { return isfinite(x) && x >= 0.0; }
 
 bool params_ok(const geo_params *p)
@@ -182,7 +185,7 @@ const char *geo_strerror(int status)
 
 int geo_workspace_size(geo_dims dims, const geo_params *p, size_t *bytes)
 {
-    if (!dims_ok(dims) || !bytes) return GEO_EINVAL;
+    if (!solver_dims_ok(dims) || !bytes) return GEO_EINVAL;
     if (p && (p->dual_storage != GEO_STORE_F32 && p->dual_storage != GEO_STORE_BF16))
         return GEO_EINVAL;
     *bytes = make_layout(dims.n1, dims.n2, dims.n3, p ? p->dual_storage : GEO_STORE_F32).total;
@@ -192,7 +195,7 @@ int geo_workspace_size(geo_dims dims, const geo_params *p, size_t *bytes)
 int geo_state_init(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
                    void *stream)
 {
-    if (!dims_ok(dims) || !params_ok(p) || !v) return GEO_EINVAL;
+    if (!solver_dims_ok(dims) || !params_ok(p) || !v) return GEO_EINVAL;
     Layout L;
     int rc = check_ws(dims, p, ws, ws_bytes, &L);
     if (rc) return rc;
@@ -221,7 +224,7 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         return GEO_EINVAL;
     std::vector<Layout> L(n);
     for (int c = 0; c < n; ++c) {
-        if (!dims_ok(dims[c]) || !params_ok(&p[c]) || !v[c]) return GEO_EINVAL;
+        if (!solver_dims_ok(dims[c]) || !params_ok(&p[c]) || !v[c]) return GEO_EINVAL;
         if (p[c].dual_storage != p[0].dual_storage) return GEO_EINVAL;
         int rc = check_ws(dims[c], &p[c], ws[c], ws_bytes[c], &L[c]);
         if (rc) return rc;
@@ -235,6 +238,9 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         int nt = 0, nb = 0;
         cube_entry(&ent[c], to_dims(dims[c]), v[c], ws[c], L[c], p[c].omega, p[c].mu_lo, p[c].mu_hi,
                    p[c].band_chunk, sh.total_tiles, sh.total_b, &nt, &nb);
+        // the workspace's per-tile regions hold every chunk band_chunk gives
+        // (make_layout); this only guards that invariant
+        if (nt > L[c].max_tiles) return GEO_EWORKSPACE;
         sh.total_tiles += nt;
         sh.total_b += nb;
         sh.shape_tiles[tile_shape(dims[c].n1, dims[c].n2, L[c].dual_bytes)] += nt;
@@ -367,7 +373,7 @@ static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *w
                      int32_t n_iter, void *stream, geo_result *out, double *phase_ms,
                      int nph = GEO_NPHASE)
 {
-    if (!dims_ok(dims) || !params_ok(p) || !v || n_iter < 0) return GEO_EINVAL;
+    if (!solver_dims_ok(dims) || !params_ok(p) || !v || n_iter < 0) return GEO_EINVAL;
     Layout L;
     int rc = check_ws(dims, p, ws, ws_bytes, &L);
     if (rc) return rc;
@@ -424,7 +430,7 @@ int geo_batch_table_size(int32_t n_cubes, size_t *bytes)
 int geo_sweep_geometry(geo_dims dims, int32_t dual_storage, int32_t requested, int32_t blocks,
                        int32_t *used_chunk, int32_t *tiles, int32_t *tile_rows, int32_t *tile_cols)
 {
-    if (!dims_ok(dims) || (dual_storage != GEO_STORE_F32 && dual_storage != GEO_STORE_BF16) ||
+    if (!solver_dims_ok(dims) || (dual_storage != GEO_STORE_F32 && dual_storage != GEO_STORE_BF16) ||
         requested < 0 || (requested == 0 && blocks < 1) || !used_chunk || !tiles || !tile_rows ||
         !tile_cols)
         return GEO_EINVAL;
@@ -434,6 +440,15 @@ int geo_sweep_geometry(geo_dims dims, int32_t dual_storage, int32_t requested, i
     *tiles = sweep_grid(dims.n1, dims.n2, dims.n3, kc, shape).blocks();
     *tile_rows = kShapeTI[shape];
     *tile_cols = kShapeTJ[shape];
+    return GEO_OK;
+}
+
+int geo_workspace_tiles(geo_dims dims, int32_t dual_storage, int32_t *max_tiles_out)
+{
+    if (!solver_dims_ok(dims) || (dual_storage != GEO_STORE_F32 && dual_storage != GEO_STORE_BF16) ||
+        !max_tiles_out)
+        return GEO_EINVAL;
+    *max_tiles_out = make_layout(dims.n1, dims.n2, dims.n3, dual_storage).max_tiles;
     return GEO_OK;
 }
 
@@ -459,7 +474,7 @@ int geo_batch_step(int32_t n_cubes, const geo_dims *dims, const geo_params *p,
 static int state_io(geo_dims dims, const void *ws, size_t ws_bytes, int32_t var, const float *v,
                     float *out, const float *in, int dual_storage, void *stream)
 {
-    if (!dims_ok(dims) || var < GEO_VAR_U || var > GEO_VAR_Y4) return GEO_EINVAL;
+    if (!solver_dims_ok(dims) || var < GEO_VAR_U || var > GEO_VAR_Y4) return GEO_EINVAL;
     if (dual_storage != GEO_STORE_F32 && dual_storage != GEO_STORE_BF16) return GEO_EINVAL;
     if ((out == nullptr) == (in == nullptr)) return GEO_EINVAL;
     geo_params p;

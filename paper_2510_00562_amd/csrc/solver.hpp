@@ -79,7 +79,7 @@ struct Layout {
     size_t total;
     int dual_bytes;
     int n_part;     // FP64 partial-sum slots: 2 per tile, then sweep B blocks
-    int max_tiles;  // sweep A tiles at the smallest band chunk
+    int max_tiles;  // most sweep A tiles of any band chunk the library may use
     int64_t cap;    // candidate capacity per field
 };
 
@@ -163,14 +163,28 @@ inline int default_chunk(int n1, int n2, int n3, int blocks, int shape)
     }
     return best;
 }
+// Pixel tiles of one band.
+inline int tiles_per_band(int n1, int n2, int shape)
+{
+    return ceil_div(n2, kShapeTJ[shape]) * ceil_div(n1, kShapeTI[shape]);
+}
+// A cube the solver takes: one band of it fits the tile limit in either
+// shape, so some band chunk always does.
+inline bool solver_dims_fit(int n1, int n2)
+{
+    for (int q = 0; q < kTileShapes; ++q)
+        if ((int64_t)ceil_div(n2, kShapeTJ[q]) * ceil_div(n1, kShapeTI[q]) > kMaxTiles) return false;
+    return true;
+}
 // Bands per tile actually used: the request (0 = the default above for
 // `blocks` persistent blocks), at least kMinKC, raised until the cube has at
-// most kMaxTiles tiles.
+// most kMaxTiles tiles (always reached for a cube that solver_dims_fit
+// takes: at kc >= n3 a cube has one band chunk).
 inline int band_chunk(int n1, int n2, int n3, int requested, int blocks, int shape)
 {
     int kc = requested > 0 ? requested : default_chunk(n1, n2, n3, blocks, shape);
     if (kc < kMinKC) kc = kMinKC;
-    while (sweep_grid(n1, n2, n3, kc, shape).blocks() > kMaxTiles) kc *= 2;
+    while (kc < n3 && sweep_grid(n1, n2, n3, kc, shape).blocks() > kMaxTiles) kc *= 2;
     return kc;
 }
 inline int point_blocks(int64_t n) { return ceil_div(n, kPointThreads); }
@@ -179,13 +193,22 @@ inline int sweep_b_blocks(int64_t n)
     int b = point_blocks(n);
     return b < kSweepBBlocks ? b : kSweepBBlocks;
 }
+// Most tiles band_chunk can give the cube, for any request and block count
+// and either shape: the tile count falls as the chunk deepens, so it is the
+// count at the shallowest chunk >= kMinKC within the limit. The per-tile
+// regions of the workspace (partials, window statistics, candidate counts)
+// are sized by it.
 inline int max_tiles(int n1, int n2, int n3)
 {
-    int m = 0;  // either tile shape
-    for (int q = 0; q < kTileShapes; ++q) {
-        const int t = sweep_grid(n1, n2, n3, band_chunk(n1, n2, n3, kMinKC, 0, q), q).blocks();
-        m = t > m ? t : m;
-    }
+    int m = 0;
+    for (int q = 0; q < kTileShapes; ++q)
+        for (int kc = kMinKC;; ++kc) {
+            const int t = sweep_grid(n1, n2, n3, kc, q).blocks();
+            if (t <= kMaxTiles || kc >= n3) {
+                m = t > m ? t : m;
+                break;
+            }
+        }
     return m;
 }
 

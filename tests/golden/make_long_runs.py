@@ -1,14 +1,22 @@
 """Writes the FP64 oracle's state after long runs, sampled, for the GPU
 parity tests at full iteration counts. Calls only oracle/ and synth/.
 
-  long_256x256x128_5000.json: the 256 x 256 x 128 benchmark cube after 5000
-  iterations of Alg. 1 from its initial point (the iteration count the
-  workload is quoted for): the last trace entry (relative change, r, tau_s,
-  tau_t), the MPSNR of u against the clean cube (eq. (29)), per-band means
-  of u, and u, s, t at 4096 seeded sample voxels.
+Runs (pick any with their names on the command line; default: all):
 
-Run from the repository root: python tests/golden/make_long_runs.py
-(about 40 minutes on 8 cores)."""
+  256    long_256x256x128_5000.json: the 256 x 256 x 128 benchmark cube after
+         5000 iterations from the initial point: the last trace entry
+         (relative change, r, tau_s, tau_t), the MPSNR of u against the clean
+         cube (eq. (29)), per-band means of u, and u, s, t at 4096 seeded
+         sample voxels. About 40 minutes on 8 cores.
+  batch  batch32_3000.json: three cubes of the 32-cube uneven batch (the
+         smallest, the largest and the one whose width fills the 64- and
+         128-column tiles worst) after 3000 iterations, the same fields for
+         each. About 40 minutes on 8 cores.
+  512    long_512x512x224_5000.json: the 512 x 512 x 224 cube after 5000
+         iterations, the same fields at checkpoints after 1, 10, 100, 1000
+         and 5000 iterations. About 5 hours on 8 cores and 31 GB of memory.
+
+Run from the repository root: python tests/golden/make_long_runs.py [runs]"""
 import json
 import os
 import sys
@@ -20,43 +28,105 @@ ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__)
 sys.path.insert(0, ROOT)
 
 import oracle  # noqa: E402
-from synth.cubes import CUBE_256x256x128, make_cube  # noqa: E402
+from synth.cubes import CUBE_256x256x128, CUBE_512x512x224, batch_specs, make_cube  # noqa: E402
 
-SAMPLES, SAMPLE_SEED, ITERS = 4096, 12345, 5000
+SAMPLES, SAMPLE_SEED = 4096, 12345
+# cubes of the uneven batch checked against the oracle: the smallest
+# (123 x 107 x 44), the largest (246 x 248 x 154) and the one of 137 columns
+# (9 columns past a whole number of 64- and of 128-column tiles)
+BATCH_CUBES = (20, 28, 4)
+BATCH_ITERS = 3000
 
 
 def sample_index(n):
     return np.sort(np.random.default_rng(SAMPLE_SEED).choice(n, size=SAMPLES, replace=False))
 
 
-def main():
-    c = make_cube(CUBE_256x256x128)
-    v = np.asarray(c["v"], dtype=np.float32).astype(np.float64)  # what the GPU sees
-    S = oracle.Solver(v, c["eps"], c["alpha"], c["beta"], omega=c["omega"])
-    t0 = time.time()
-    for done in range(0, ITERS, 500):
-        S.step(500)
-        print(f"{done + 500} iterations, {time.time() - t0:.0f} s, rel {S.trace[-1][0]:.3e}",
-              flush=True)
-    idx = sample_index(v.size)
-    out = {
-        "cube": "256x256x128", "iterations": ITERS, "omega": c["omega"],
-        "eps": c["eps"], "alpha": c["alpha"], "beta": c["beta"],
+def snapshot(S, u_clean, idx, iters):
+    return {
+        "iterations": iters,
         "last_trace": {"rel": S.trace[-1][0], "r": S.trace[-1][1], "tau_s": S.trace[-1][2],
                        "tau_t": S.trace[-1][3]},
-        "mpsnr": oracle.mpsnr(S.u, c["u_clean"]),
+        "mpsnr": oracle.mpsnr(S.u, u_clean),
         "band_mean_u": S.u.reshape(S.u.shape[0], -1).mean(axis=1).tolist(),
-        "sample_seed": SAMPLE_SEED,
-        "sample_index": idx.tolist(),
         "u": S.u.ravel()[idx].tolist(),
         "s": S.s.ravel()[idx].tolist(),
         "t": S.t.ravel()[idx].tolist(),
     }
-    path = os.path.join(ROOT, "tests", "golden", "long_256x256x128_5000.json")
+
+
+def solver_for(c):
+    v = np.asarray(c["v"], dtype=np.float32).astype(np.float64)  # what the GPU sees
+    return oracle.Solver(v, c["eps"], c["alpha"], c["beta"], omega=c["omega"])
+
+
+def run_to(S, label, target, t0, every=100):
+    while len(S.trace) < target:
+        S.step(min(every, target - len(S.trace)))
+        print(f"{label}: {len(S.trace)} iterations, {time.time() - t0:.0f} s, "
+              f"rel {S.trace[-1][0]:.3e}", flush=True)
+
+
+def write(name, out):
+    path = os.path.join(ROOT, "tests", "golden", name)
     with open(path, "w") as f:
         json.dump(out, f)
-    print("wrote", path)
+    print("wrote", path, flush=True)
 
+
+def run_256():
+    c = make_cube(CUBE_256x256x128)
+    S = solver_for(c)
+    t0 = time.time()
+    run_to(S, "256x256x128", 5000, t0, every=500)
+    idx = sample_index(S.u.size)
+    out = {"cube": "256x256x128", "omega": c["omega"], "eps": c["eps"], "alpha": c["alpha"],
+           "beta": c["beta"], "sample_seed": SAMPLE_SEED, "sample_index": idx.tolist()}
+    out.update(snapshot(S, c["u_clean"], idx, 5000))
+    write("long_256x256x128_5000.json", out)
+
+
+def run_batch():
+    specs = batch_specs()
+    cubes = []
+    for q in BATCH_CUBES:
+        sp = specs[q]
+        c = make_cube(sp)
+        S = solver_for(c)
+        t0 = time.time()
+        run_to(S, f"batch cube {q} ({sp.n1}x{sp.n2}x{sp.n3})", BATCH_ITERS, t0, every=250)
+        idx = sample_index(S.u.size)
+        e = {"index": q, "n1": sp.n1, "n2": sp.n2, "n3": sp.n3, "eps": c["eps"],
+             "alpha": c["alpha"], "beta": c["beta"], "omega": c["omega"],
+             "sample_index": idx.tolist()}
+        e.update(snapshot(S, c["u_clean"], idx, BATCH_ITERS))
+        cubes.append(e)
+        del S, c
+    write("batch32_3000.json", {"iterations": BATCH_ITERS, "sample_seed": SAMPLE_SEED,
+                                "cubes": cubes})
+
+
+def run_512():
+    c = make_cube(CUBE_512x512x224)
+    u_clean = c["u_clean"]
+    S = solver_for(c)
+    head = {"cube": "512x512x224", "omega": c["omega"], "eps": c["eps"], "alpha": c["alpha"],
+            "beta": c["beta"], "sample_seed": SAMPLE_SEED}
+    del c
+    idx = sample_index(S.u.size)
+    head["sample_index"] = idx.tolist()
+    t0 = time.time()
+    checkpoints = []
+    for target in (1, 10, 100, 1000, 5000):
+        run_to(S, "512x512x224", target, t0)
+        checkpoints.append(snapshot(S, u_clean, idx, target))
+        # partial file after every checkpoint, so a long run leaves something
+        write("long_512x512x224_5000.json", dict(head, checkpoints=checkpoints,
+                                                  complete=target == 5000))
+
+
+RUNS = {"256": run_256, "batch": run_batch, "512": run_512}
 
 if __name__ == "__main__":
-    main()
+    for name in (sys.argv[1:] or list(RUNS)):
+        RUNS[name]()

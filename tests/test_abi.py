@@ -143,3 +143,48 @@ def test_tile_shape_follows_the_fill(shape, rows_cols):
     assert (ti, tj) == rows_cols
     assert tiles == -(-n1 // ti) * -(-n2 // tj) * -(-n3 // kc)
     assert geo.geo_sweep_geometry(d, 16, dual_storage=geo.GEO_STORE_BF16)[2:] == (8, 128)
+
+
+def test_workspace_holds_every_band_chunk():
+    """The per-tile regions of a solver workspace hold the tiles of every
+    band chunk the library can pick: any request (512 x 512 x 224 at 14
+    bands has 4096 tiles, more than the 3584 of the doubled minimum chunk)
+    and the default chunk for any block count (160 x 864 x 300 on 256 blocks
+    picks 15 bands: 2800 tiles). Host-only."""
+    import numpy as np
+
+    import paper_2510_00562_amd as geo
+    big = geo.dims_of((224, 512, 512))
+    assert geo.geo_sweep_geometry(big, 14)[:2] == (14, 4096)
+    assert geo.geo_sweep_geometry(big, 15)[:2] == (15, 3840)
+    assert geo.geo_workspace_tiles(big) >= 4096
+    odd = geo.dims_of((300, 160, 864))
+    kc, tiles, _, _ = geo.geo_sweep_geometry(odd, 0, 256)
+    assert tiles <= geo.geo_workspace_tiles(odd), (kc, tiles)
+    rng = np.random.default_rng(5)
+    shapes = [(int(rng.integers(1, 400)), int(rng.integers(1, 700)), int(rng.integers(1, 900)))
+              for _ in range(40)] + [(224, 512, 512), (300, 160, 864), (1, 2048, 2048)]
+    for shape in shapes:
+        d = geo.dims_of(shape)
+        for ds in (geo.GEO_STORE_F32, geo.GEO_STORE_BF16):
+            cap = geo.geo_workspace_tiles(d, ds)
+            worst = max(geo.geo_sweep_geometry(d, kc, dual_storage=ds)[1]
+                        for kc in range(1, shape[0] + 2))
+            worst = max([worst] + [geo.geo_sweep_geometry(d, 0, b, dual_storage=ds)[1]
+                                   for b in (8, 64, 200, 256, 512, 1024)])
+            assert worst <= cap, (shape, ds, worst, cap)
+
+
+def test_bands_beyond_the_tile_limit_are_rejected():
+    """One band of more than 4096 tiles (here 4096 x 4096 pixels) cannot be
+    swept: the solver entry points refuse it instead of looping on the band
+    chunk; 2048 x 2048 is the largest square band."""
+    import paper_2510_00562_amd as geo
+    L = geo.lib()
+    n = ctypes.c_size_t()
+    x = ctypes.c_int32()
+    assert L.geo_workspace_size(geo.geo_dims(4096, 4096, 1), None, ctypes.byref(n)) == -1
+    assert L.geo_workspace_tiles(geo.geo_dims(4096, 4096, 1), 0, ctypes.byref(x)) == -1
+    assert L.geo_sweep_geometry(geo.geo_dims(4096, 4096, 1), 0, 8, 256, *[ctypes.byref(x)] * 4) == -1
+    assert L.geo_workspace_size(geo.geo_dims(2048, 2048, 3), None, ctypes.byref(n)) == 0
+    assert geo.geo_sweep_geometry(geo.geo_dims(2048, 2048, 3), 8)[:2] == (8, 4096)
