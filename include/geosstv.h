@@ -106,6 +106,9 @@ typedef struct {
                                 predicted window missed) during the call   */
     int32_t cand_s, cand_t;  /* values inside the predicted windows in the
                                 last iteration (diagnostic)                */
+    int32_t slots;       /* launch slots the call issued (one iteration of
+                            every working cube each; a missed window is
+                            resolved inside its slot)                       */
 } geo_result;
 
 /* Workspace of a solver state for one cube (bytes, 256-byte aligned base

@@ -51,7 +51,8 @@ class geo_result(ctypes.Structure):
                 ("rel_change", ctypes.c_double), ("r", ctypes.c_double),
                 ("tau_s", ctypes.c_double), ("tau_t", ctypes.c_double),
                 ("total_iters", ctypes.c_int32), ("fallback_passes", ctypes.c_int32),
-                ("cand_s", ctypes.c_int32), ("cand_t", ctypes.c_int32)]
+                ("cand_s", ctypes.c_int32), ("cand_t", ctypes.c_int32),
+                ("slots", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}

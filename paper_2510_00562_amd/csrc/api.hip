@@ -35,12 +35,13 @@ Layout make_layout(int n1, int n2, int n3, int dual_storage)
     };
     L.scalars = take(sizeof(DevScalars));
     L.partials = take(sizeof(double) * (size_t)L.n_part);
-    L.hist = take(2 * sizeof(Hist));
+    L.hist = take(6 * sizeof(Hist));  // 3 radix levels x 2 fields
+    L.rec = take(6 * sizeof(FbRec));
     L.y4p = take(fd);
     L.winpart = take(sizeof(double) * 2 * 3 * (size_t)L.max_tiles);
     L.cand = take(sizeof(float) * 2 * (size_t)L.cap);
     L.ccount = take(sizeof(uint32_t) * 2 * (size_t)L.max_tiles);
-    L.table = take(sizeof(CubeEntry));
+    L.table = take(table_bytes(1));
     for (int p = 0; p < 2; ++p) {
         L.u[p] = take(f4);
         L.s[p] = take(f4);
@@ -205,18 +206,20 @@ int geo_state_init(geo_dims dims, const geo_params *p, const float *v, void *ws,
 
 // One solver call over n cubes (n = 1: the single-cube entry points). The
 // launch table (host image `ent`, device copy at `table`) is written once;
-// each launch slot (sweep A, search, sweep B, finalize) completes one
-// iteration of every busy cube, except the slots in which a cube runs the
-// radix levels of a threshold search whose predicted window missed. The
-// loop tops up slots until every cube has done n_iter iterations (the device
-// idles a cube after them) or met its stopping rule.
+// each launch slot (sweep A, search, the three histogram passes of a missed
+// window, sweep B, finalize) completes one iteration of every busy cube.
+// With a tolerance the host reads the stopping flags every check_every
+// slots; the device idles a cube once it has met its rule or done n_iter
+// iterations.
 // phase_ms (may be null): nph = GEO_NPHASE phase times (4 events in every
 // slot), or nph = 1 for sweep A alone: 2 events around it in every
-// kTimedEvery-th slot, the sampled times scaled to all slots (an event
-// pair costs a few microseconds of idle time between the launches it
-// brackets, which sampling keeps out of most iterations).
+// kTimedEvery-th slot, from the kTimedEvery-th on (the first slot of a call
+// follows a host synchronisation and starts from an idle device), the
+// sampled times scaled to all slots (an event pair costs a few
+// microseconds of idle time between the launches it brackets, which
+// sampling keeps out of most iterations).
 static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const float *const *v,
-                     void *const *ws, const size_t *ws_bytes, void *table, size_t table_bytes,
+                     void *const *ws, const size_t *ws_bytes, void *table, size_t table_bytes_given,
                      int32_t n_iter, int use_graph, hipStream_t st, geo_result *out,
                      double *phase_ms, int nph = GEO_NPHASE)
 {
@@ -229,8 +232,7 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         int rc = check_ws(dims[c], &p[c], ws[c], ws_bytes[c], &L[c]);
         if (rc) return rc;
     }
-    if (!table || ((uintptr_t)table & 255u) || table_bytes < (size_t)n * sizeof(CubeEntry))
-        return GEO_EWORKSPACE;
+    if (!table || ((uintptr_t)table & 255u) || table_bytes_given < table_bytes(n)) return GEO_EWORKSPACE;
     std::vector<CubeEntry> ent(n);
     LaunchShape sh{};
     sh.ncubes = n;
@@ -246,15 +248,19 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         sh.shape_tiles[tile_shape(dims[c].n1, dims[c].n2, L[c].dual_bytes)] += nt;
     }
     sh.grid_a = sweep_a_grid(L[0].dual_bytes, sh.total_tiles);
+    sh.fb_grid = fallback_grid();
     for (int q = 0; q < kTileShapes; ++q)
         sh.shape_grid[q] = sh.shape_tiles[q] > 0 ? sweep_a_grid(L[0].dual_bytes, sh.shape_tiles[q]) : 0;
-    int rc = hip_status(hipMemcpyAsync(table, ent.data(), (size_t)n * sizeof(CubeEntry),
-                                       hipMemcpyHostToDevice, st));
+    // the entries, then the launch flags zeroed
+    std::vector<unsigned char> img(table_bytes(n), 0);
+    memcpy(img.data(), ent.data(), (size_t)n * sizeof(CubeEntry));
+    int rc = hip_status(hipMemcpyAsync(table, img.data(), img.size(), hipMemcpyHostToDevice, st));
     for (int c = 0; c < n && !rc; ++c)
         rc = hip_status(launch_begin_call(ws[c], L[c], p[c].tol, p[c].alpha, p[c].beta, n_iter, st));
     if (rc) return rc;
     const int nev = nph == 1 ? 2 : 4;
-    const int ev_every = nph == 1 ? kTimedEvery : 1;
+    // calls shorter than the sampling period time every slot
+    const int ev_every = nph == 1 && n_iter >= kTimedEvery ? kTimedEvery : 1;
     long slots = 0, sampled = 0;
     if (phase_ms)
         for (int q = 0; q < nph; ++q) phase_ms[q] = 0.0;
@@ -313,7 +319,7 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         }
         int nsamp = 0;  // slots of this batch with events, in order
         for (int q = 0; q < batch && !rc; ++q) {
-            const bool timed = phase_ms && (slots + q) % ev_every == 0;
+            const bool timed = phase_ms && (slots + q) % ev_every == ev_every - 1;
             if (gexec)
                 rc = hip_status(hipGraphLaunch(gexec, st));
             else
@@ -362,6 +368,7 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
             o.fallback_passes = (int32_t)x.fallback;
             o.cand_s = (int32_t)x.sel[0].cand_count;
             o.cand_t = (int32_t)x.sel[1].cand_count;
+            o.slots = (int32_t)slots;
         }
         if (x.nonfinite) status = GEO_ENONFINITE;
         else if (status == GEO_OK && p[c].tol > 0.0 && !x.stop) status = GEO_MAXITER;
@@ -378,7 +385,7 @@ static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *w
     int rc = check_ws(dims, p, ws, ws_bytes, &L);
     if (rc) return rc;
     void *table = (char *)ws + L.table;
-    return run_cubes(1, &dims, p, &v, &ws, &ws_bytes, table, sizeof(CubeEntry), n_iter, 0, S(stream),
+    return run_cubes(1, &dims, p, &v, &ws, &ws_bytes, table, table_bytes(1), n_iter, 0, S(stream),
                      out, phase_ms, nph);
 }
 
@@ -423,7 +430,7 @@ int geo_solve(geo_dims dims, const geo_params *p, const float *v, float *u, floa
 int geo_batch_table_size(int32_t n_cubes, size_t *bytes)
 {
     if (n_cubes < 1 || n_cubes > kMaxBatch || !bytes) return GEO_EINVAL;
-    *bytes = align256((size_t)n_cubes * sizeof(CubeEntry));
+    *bytes = table_bytes(n_cubes);
     return GEO_OK;
 }
 

@@ -14,7 +14,7 @@
 // Bin sums are exact: all values of a level-0 bin share one exponent, so their
 // sum is an integer sum of 24-bit significands (u64 atomics, order free),
 // scaled by a power of two. Histograms are therefore bitwise deterministic.
-#include "solver.hpp"
+#include "radix.hpp"
 
 namespace geo {
 
@@ -96,35 +96,6 @@ __global__ __launch_bounds__(kSelThreads) void k_hist(Src src, int64_t n, const 
             atomicAdd((unsigned long long *)&hist[f].msum[b], ms[b]);
         }
     }
-}
-
-// Window for the next iteration: tau is extrapolated linearly from the last
-// two levels, and the half-width is three times the error the same
-// extrapolation made for this iteration (plus 2e-4 tau, and never less than
-// the last step when the history is short or the prediction failed).
-__device__ void set_window(SelState &o, bool missed)
-{
-    const double tau = o.tau;
-    if (!(tau > 0.0) || !isfinite(tau)) {
-        o.win_on = 0u;
-        o.tau_prev2 = 0.0;
-        o.tau_prev = tau;
-        return;
-    }
-    const double t1 = o.tau_prev, t2 = o.tau_prev2;
-    const bool h1 = t1 > 0.0 && isfinite(t1), h2 = h1 && t2 > 0.0 && isfinite(t2);
-    const double step = h1 ? tau - t1 : 0.05 * tau;
-    const double err = h2 ? fabs(tau - (2.0 * t1 - t2)) : fabs(step);
-    double h = 3.0 * err + 2e-4 * tau;
-    if (!h2 || missed) h = fmax(h, fabs(step) + 2e-4 * tau);
-    const double c = tau + (h1 ? step : 0.0);
-    double lo = c - h, hi = c + h;
-    if (lo < 0.0) lo = 0.0;
-    o.win_lo = __double2float_rd(lo);
-    o.win_hi = __double2float_ru(hi);
-    o.win_on = 1u;
-    o.tau_prev2 = h1 ? t1 : 0.0;
-    o.tau_prev = tau;
 }
 
 // One block per field: pick the bin that holds tau, or finish.
@@ -260,7 +231,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_level(SelState *sel, His
             o.level = (uint32_t)(level + 1);
         }
     }
-    if (o.done) set_window(o, true);
+    if (o.done) set_window(o, true, 0.0);
     sel[f] = o;
     fin = o.done;
     }
@@ -390,122 +361,6 @@ __device__ __forceinline__ double bin_value(unsigned long long msum, uint32_t fi
     return (double)msum * ldexp(1.0, (int)(e ? e : 1u) - 150);
 }
 
-// One radix level of the full search for field f (one block of kWinThreads):
-// the bins of the level are scanned in parallel from the top with exact
-// integer bin sums; the bin holding tau either finishes the search (empty,
-// one value, or single-pattern bins at level 2) or becomes the next range.
-__device__ void level_step(SelState *sel, Hist *hist, int f)
-{
-    __shared__ SelState s;
-    __shared__ double wsd[3 * (kWinThreads / 64)];
-    __shared__ int best;
-    __shared__ int fin;
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        s = sel[f];
-        best = -1;
-        fin = 0;
-    }
-    __syncthreads();
-    const int level = (int)s.level;
-    const int nb = lvl_bins(level), shift = lvl_shift(level);
-    const int per = nb / kWinThreads;  // 2 or 1 bins per thread, taken from the top
-    const uint32_t base = level == 0 ? 0u : (s.prefix << (level == 1 ? 20 : 10));
-    const int btop = nb - 1 - per * tid;
-    double ts = 0.0, tc = 0.0;
-    for (int q = 0; q < per; ++q) {
-        const int b = btop - q;
-        const uint32_t e = lvl_exponent(level, s.prefix, b);
-        ts += (double)hist[f].msum[b] * ldexp(1.0, (int)(e ? e : 1u) - 150);
-        tc += (double)hist[f].count[b];
-    }
-    double allS, allC;
-    double xS = ts, xC = tc;
-    block_exclusive_scan2(xS, xC, wsd, allS, allC);
-    double S = s.s_above + xS;
-    double C = (double)s.c_above + xC;
-    const double radius = s.radius;
-    int mine = -1;
-    double mS = 0.0, mC = 0.0, mbs = 0.0, mbc = 0.0, mfb = 0.0;
-    for (int q = 0; q < per; ++q) {
-        const int b = btop - q;
-        const uint32_t e = lvl_exponent(level, s.prefix, b);
-        const double bs = (double)hist[f].msum[b] * ldexp(1.0, (int)(e ? e : 1u) - 150);
-        const double bc = (double)hist[f].count[b];
-        const float eb = __uint_as_float(base | ((uint32_t)b << shift));
-        const double fb = (S + bs) - (double)eb * (C + bc);
-        if (fb >= radius) {
-            mine = b;
-            mS = S;  // strictly above bin b
-            mC = C;
-            mbs = bs;
-            mbc = bc;
-            mfb = fb;
-            break;
-        }
-        S += bs;
-        C += bc;
-    }
-    {
-        int wm = mine;  // one atomic per wavefront
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) wm = max(wm, __shfl_xor(wm, o, 64));
-        if ((threadIdx.x & 63) == 0 && wm >= 0) atomicMax(&best, wm);
-    }
-    __syncthreads();
-    int b = best;
-    bool owner = b >= 0 && mine == b;
-    if (b < 0 && level > 0 && tid == kWinThreads - 1) {
-        // FP64 rounding at the lower edge of a deeper range: take bin 0
-        owner = true;
-        b = 0;
-        const uint32_t e = lvl_exponent(level, s.prefix, 0);
-        mbs = (double)hist[f].msum[0] * ldexp(1.0, (int)(e ? e : 1u) - 150);
-        mbc = (double)hist[f].count[0];
-        mS = (s.s_above + allS) - mbs;
-        mC = ((double)s.c_above + allC) - mbc;
-        mfb = (mS + mbs) - (double)__uint_as_float(base) * (mC + mbc);
-    }
-    if (b < 0 && level == 0 && tid == 0) {
-        // sum |z| <= radius: inside the ball
-        SelState o = s;
-        o.tau = 0.0;
-        o.done = 1u;
-        set_window(o, true);
-        sel[f] = o;
-        fin = 1;
-    }
-    if (owner) {
-        SelState o = s;
-        const float eb = __uint_as_float(base | ((uint32_t)b << shift));
-        if (mfb == radius) {
-            o.tau = (double)eb;
-            o.done = 1u;
-        } else if (mbc == 0.0 || level == 2) {
-            o.tau = (mS - radius) / mC;
-            o.done = 1u;
-        } else if (mbc == 1.0) {
-            const double t1 = mC > 0.0 ? (mS - radius) / mC : -1.0;
-            o.tau = (mC > 0.0 && t1 >= mbs) ? t1 : (mS + mbs - radius) / (mC + 1.0);
-            o.done = 1u;
-        } else {
-            o.prefix = (level == 0 ? 0u : (s.prefix << 10)) | (uint32_t)b;
-            o.c_above = (uint64_t)mC;
-            o.s_above = mS;
-            o.level = (uint32_t)(level + 1);
-        }
-        if (o.done) set_window(o, true);
-        sel[f] = o;
-        fin = o.done ? 1 : 0;
-    }
-    __syncthreads();
-    if (!fin)  // the next level accumulates into a clean histogram
-        for (int q = tid; q < kHistBins; q += kWinThreads) {
-            hist[f].count[q] = 0u;
-            hist[f].msum[q] = 0ull;
-        }
-}
-
 #ifndef GEO_PREFETCH_BUDGET
 #define GEO_PREFETCH_BUDGET 96  // MB, of the 256 MB memory-side cache
 #endif
@@ -613,10 +468,9 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
     const int tid = threadIdx.x;
     // Every first read goes out at once: the cube's flags, the field's search
     // state (a word per thread) and sweep A's tile partials and candidate
-    // counts (fixed order). A cube that turns out idle, or that is in a
-    // radix pass of the full search, has read a few KB for nothing.
+    // counts (fixed order). A cube that turns out idle has read a few KB for
+    // nothing.
     const bool is_idle = idle(sc);
-    const uint32_t in_hist_slot = sc->hist_slot;
     constexpr int kSelWords = sizeof(SelState) / 4;
     static_assert(sizeof(SelState) % 4 == 0 && kSelWords <= kWinThreads, "search state by words");
     const uint32_t sel_word = tid < kSelWords ? reinterpret_cast<const uint32_t *>(&sel[f])[tid] : 0u;
@@ -645,11 +499,6 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         mine += cb;
     }
     if (is_idle) return;
-    if (in_hist_slot) {  // sweep A histogrammed a radix level of a running search
-        if (sel[f].done) return;
-        level_step(sel, hist, f);
-        return;
-    }
     if (tid < kSelWords) reinterpret_cast<uint32_t *>(&s)[tid] = sel_word;
     if (tid == 0) {
         ovf = 0u;
@@ -928,9 +777,13 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
         if (verdict == 1) {
             o.done = 1u;
             o.full = 0u;
-            set_window(o, false);
+            // density of |z| in this iteration's window, for the next one's size
+            const double wdt = (double)s.win_hi - (double)s.win_lo;
+            o.dens = (s.win_on && wdt > 0.0) ? (double)o.cand_count / wdt : 0.0;
+            set_window(o, false, window_budget(cc.d.plane));
         } else {
-            // full radix search on the whole field
+            // the radix levels over the whole field, by the histogram passes
+            // that follow in this launch slot (fallback.hip)
             o.done = 0u;
             o.full = 1u;
             o.level = 0u;
@@ -939,13 +792,15 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
             o.s_above = 0.0;
             o.win_on = 0u;
             atomicAdd(fallback_counter, 1u);
+            *slot_flags(table, ncubes) = 1u;  // the histogram passes run
         }
         sel[f] = o;
     }
-    if (verdict != 1)
-        for (int q = tid; q < kHistBins; q += kWinThreads) {
-            hist[f].count[q] = 0u;
-            hist[f].msum[q] = 0ull;
+    if (verdict != 1)  // the passes accumulate into clean histograms
+        for (int q = tid; q < 3 * kHistBins; q += kWinThreads) {
+            Hist &h = hist[(q / kHistBins) * 2 + f];
+            h.count[q % kHistBins] = 0u;
+            h.msum[q % kHistBins] = 0ull;
         }
 }
 

@@ -16,8 +16,8 @@ namespace geo {
 // |z| inside a window [win_lo, win_hi] predicted from the last two levels
 // (candidates) plus the count and sum of the values above it, and one block
 // finishes the search exactly over the candidates. When the window misses,
-// a radix search over the FP32 bit patterns of the whole field runs instead
-// (see select.hip).
+// a radix search over the FP32 bit patterns of the whole field runs instead,
+// in the same launch slot (fallback.hip, radix.hpp).
 struct SelState {
     double radius;     // radius of the l1 ball
     double s_above;    // radix search: sum of |z| above the current bit range
@@ -32,6 +32,8 @@ struct SelState {
     float win_lo, win_hi;  // window used by the next sweep A
     uint32_t win_on;       // window valid
     uint32_t cand_count;   // candidates in the window (search bookkeeping)
+    double dens;           // values of |z| per unit near tau in the last
+                           // iteration (sizes the next window)
 };
 
 constexpr int kHistBins = 2048;  // bins of radix level 0 (levels 1 and 2 use 1024)
@@ -42,6 +44,25 @@ struct Hist {
     uint32_t count[kHistBins];
     uint64_t msum[kHistBins];
 };
+
+// Outcome of one radix level of a field whose window missed, written by the
+// histogram pass of that level (fallback.hip) and read by the next pass,
+// sweep B and the finalize of the same launch slot.
+struct FbRec {
+    double tau;      // the threshold, when the level ended the search
+    double s_above;  // sum and count of the values above the chosen bin
+    double c_above;
+    double dens;     // values per unit of |z| in tau's level-0 bin (level 0)
+    uint32_t prefix; // bits fixed so far (the chosen bins)
+    uint32_t done;   // the level ended the search
+};
+
+// The threshold of a field that missed its window, from the records of this
+// slot's passes: the first level that ended the search.
+__host__ __device__ inline const FbRec &fb_final(const FbRec *rec, int f)
+{
+    return rec[0 * 2 + f].done ? rec[0 * 2 + f] : (rec[1 * 2 + f].done ? rec[1 * 2 + f] : rec[2 * 2 + f]);
+}
 
 // Scalars of the iteration kept on the device. y4 is stored as the residual
 // q = 5 y4' - v with y4 = a4 * q: the fidelity-ball step of Alg. 1 (steps
@@ -60,7 +81,6 @@ struct DevScalars {
     uint32_t calls_iter; // iterations done in the current geo_step call
     SelState sel[2];     // 0: s (alpha), 1: t (beta)
     uint32_t fallback;   // full radix searches in the current call
-    uint32_t hist_slot;  // 1: sweep A of this launch slot ran a search histogram
     uint32_t call_limit; // iterations this call may do: the cube idles after them
 };
 
@@ -73,7 +93,7 @@ __device__ __forceinline__ bool idle(const DevScalars *sc)
 
 // Offsets (bytes) of every region of a solver workspace.
 struct Layout {
-    size_t scalars, partials, hist, y4p, winpart, cand, ccount, table;
+    size_t scalars, partials, hist, rec, y4p, winpart, cand, ccount, table;
     size_t u[2], s[2], t[2], w1[2], w2[2];  // FP32 primal, ping-pong
     size_t y1[2], y2[2], y3[2], y4[2];      // duals (FP32 or BF16), ping-pong
     size_t total;
@@ -240,7 +260,8 @@ struct CubeCommon {
     DevScalars *sc;
     double *part;       // [2 * ntiles] tile partials (du2, u2), then sweep B blocks
     double *winpart;    // [2][ntiles][3] count above, sum above, sum of |z|
-    Hist *hist;         // [2] histograms of the full threshold search
+    Hist *hist;         // [3 levels][2 fields] histograms of the full threshold search
+    FbRec *rec;         // [3 levels][2 fields] their outcomes
     float *cand;        // [2][ntiles][capt] candidate slices of the tiles
     uint32_t *ccount;   // [2][ntiles] candidates appended by each tile
     int capt;           // candidate capacity of one tile slice
@@ -302,6 +323,7 @@ struct LaunchShape {
     int total_b;      // sweep B blocks over all cubes
     int shape_tiles[kTileShapes];  // sweep A tiles of the cubes of each tile shape
     int shape_grid[kTileShapes];   // persistent blocks of the sweep A launch of each shape
+    int fb_grid;      // blocks of each fallback histogram pass
 };
 
 // Host image of one cube's table entry (FP32 or BF16 duals: same size).
@@ -309,6 +331,24 @@ struct CubeEntry {
     unsigned char bytes[sizeof(CubeArgs<float>)];
 };
 static_assert(sizeof(CubeArgs<float>) == sizeof(CubeArgs<bf16>), "one table entry size");
+
+// Launch-wide words of a table, in the 512 bytes after its entries (the
+// table upload zeroes them). Word 0: set by the window search when some
+// threshold of the slot missed its window, cleared by the finalize; the
+// histogram passes leave at once when it is 0. Words 64 + c (their own
+// cache lines, touched only by atomics of system scope): blocks of the
+// running histogram pass done with cube c.
+constexpr size_t kTableFlagBytes = 512;
+constexpr int kFbCounterWord = 64;
+__host__ __device__ inline size_t table_flags_offset(int ncubes)
+{
+    return ((size_t)ncubes * sizeof(CubeEntry) + 255) & ~(size_t)255;
+}
+__host__ __device__ inline uint32_t *slot_flags(const void *table, int ncubes)
+{
+    return (uint32_t *)((char *)table + table_flags_offset(ncubes));
+}
+__host__ __device__ inline size_t table_bytes(int ncubes) { return table_flags_offset(ncubes) + kTableFlagBytes; }
 
 // ---- launchers (kernels in sweep.hip / select.hip / ops.hip) ----
 hipError_t launch_init(const Dims &d, const float *v, void *ws, const Layout &L, double eps,
@@ -347,6 +387,12 @@ hipError_t launch_soft(const float *x, int64_t n, const SelState *sel, float *ou
 // memory-side cache meanwhile (prefetch_blocks, 0 = none).
 hipError_t launch_select_window(const void *table, int stride, int ncubes, int prefetch_blocks,
                                 hipStream_t st);
+
+// The histogram pass of radix level `level` (0..2) for the thresholds whose
+// window missed in this slot (fallback.hip); a no-op when none did.
+int fallback_grid();
+hipError_t launch_fallback(const void *table, int dual_bytes, const LaunchShape &sh, int level,
+                           hipStream_t st);
 
 // Standalone projections (ops.hip).
 int l2_blocks(int64_t n);

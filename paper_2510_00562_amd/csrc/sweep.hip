@@ -28,7 +28,7 @@
 // remaining launches into no-ops, so iteration counts stay exact.
 #include <string.h>
 
-#include "solver.hpp"
+#include "radix.hpp"
 
 namespace geo {
 
@@ -104,66 +104,6 @@ __device__ __forceinline__ int tile_at(int b, int G, int T, int r)
     return t < T ? t : -1;
 }
 
-// One radix level of the full threshold search over z evaluated from the
-// state (bit-identical to the sweeps' own evaluation) on one tile, for every
-// field of the cube whose search is still running; LDS histograms flushed
-// with integer atomics.
-template <typename DT, int S>
-__device__ void tile_histogram(const4<CubeArgs<DT>> &a, int i0, int j0, int kb, int ke, float *smem)
-{
-    GEO_TILE_GEOMETRY(S);
-    const DevScalars *sc = a.c.sc;
-    uint32_t *hc = reinterpret_cast<uint32_t *>(smem);                              // [2][2048]
-    unsigned long long *hm = reinterpret_cast<unsigned long long *>(smem + 2 * kHistBins);  // [2][2048]
-    for (int b = threadIdx.x; b < 2 * kHistBins; b += NT) {
-        hc[b] = 0u;
-        hm[b] = 0ull;
-    }
-    bool act[2];
-    int lvl[2];
-    uint32_t pre[2];
-    for (int f = 0; f < 2; ++f) {
-        act[f] = sc->sel[f].done == 0u;
-        lvl[f] = (int)sc->sel[f].level;
-        pre[f] = sc->sel[f].prefix;
-    }
-    __syncthreads();
-    const Dims d = load_dims(a.c.d);
-    const int n1 = d.n1, n2 = d.n2;
-    const int par = (int)(sc->iter & 1u);
-    const Side<DT> src = load_side(a.side[par]);
-    const float a4 = (float)sc->a4;
-    auto add = [&](int f, float z) {
-        const uint32_t p = abs_bits(z);
-        const int L = lvl[f], sh = lvl_shift(L);
-        if (L > 0 && (p >> (sh + 10)) != pre[f]) return;
-        const uint32_t b = (p >> sh) & (uint32_t)(lvl_bins(L) - 1);
-        atomicAdd(&hc[f * kHistBins + b], 1u);
-        atomicAdd(&hm[f * kHistBins + b], (unsigned long long)significand(p));
-    };
-    const int i = i0 + (int)threadIdx.x / TJ, j = j0 + (int)threadIdx.x % TJ;
-    if (i < n1 && j < n2)
-        for (int k = kb; k < ke; ++k) {
-            const uint32_t q = ((uint32_t)k * (uint32_t)n1 + (uint32_t)i) * (uint32_t)n2 + (uint32_t)j;
-            const float y4 = y4_of(ld(src.y4 + q), a4);
-            if (act[0]) add(0, zs_of(src.s[q], y4));
-            if (act[1]) {
-                const float y3c = i <= n1 - 2 ? ld(src.y3 + q) : 0.f;
-                const float y3m = i >= 1 ? ld(src.y3 + q - n2) : 0.f;
-                add(1, zt_of(src.t[q], y3m, y3c, y4));
-            }
-        }
-    __syncthreads();
-    for (int b = threadIdx.x; b < 2 * kHistBins; b += NT) {
-        const int f = b / kHistBins, bb = b - f * kHistBins;
-        if (hc[b]) {
-            atomicAdd(&a.c.hist[f].count[bb], hc[b]);
-            atomicAdd((unsigned long long *)&a.c.hist[f].msum[bb], hm[b]);
-        }
-    }
-    __syncthreads();
-}
-
 // Sums of 8 FP64 values over the block; result valid in thread 0.
 __device__ __forceinline__ void block_sum8(double (&x)[8], double *red /* 8 * NT/64 */)
 {
@@ -197,7 +137,6 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
     __shared__ double red[8 * (NT / 64)];
     __shared__ uint32_t ncand[2];
     __shared__ int tile0[kMaxBatch + 1];
-    static_assert(sizeof(smem) >= 2 * kHistBins * 12, "LDS holds the search histograms");
 
     // The tiles of the cubes of this tile shape that work in this slot, one
     // cube after another: a cube that idles takes none, so the persistent
@@ -255,17 +194,6 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
         const Dims d = load_dims(a.c.d);
         const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
         const int ke = min(kb + g.kc, n3);
-
-        // A threshold search that missed its window runs its radix levels in
-        // the launch slots that follow; the cube's tiles then only histogram
-        // z for the field(s) still searching, and the rest of the slot
-        // completes the iteration once both levels are final.
-        if (!(sc->sel[0].done && sc->sel[1].done)) {
-            if (tid == 0) sc->hist_slot = 1u;
-            tile_histogram<DT, S>(a, i0, j0, kb, ke, smem);
-            continue;
-        }
-        if (tid == 0) sc->hist_slot = 0u;
 
         const uint32_t N = (uint32_t)d.plane;
         if (tid < 2) ncand[tid] = 0u;  // published by the first barrier of the march
@@ -390,9 +318,9 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
                     st_nt(dst.u + q, un);
                     // 5 (y4 + u'/5) - v: step 14 without s', t', times 5, minus v
                     st_nt(a.y4p + q, (5.f * y4 + up) - ru_v);
-                    const float dl = un - ru_u;
-                    du2 += (double)(dl * dl);
-                    u2 += (double)(ru_u * ru_u);
+                    const double dl = (double)un - (double)ru_u;
+                    du2 += dl * dl;
+                    u2 += (double)ru_u * (double)ru_u;
                     zs = zs_of(ru_s, y4);
                     zt = zt_of(ru_t, ru_y3m, ru_y3c, y4);
                 }
@@ -636,14 +564,14 @@ __device__ __forceinline__ void stv_nt(bf16 *p, const float (&x)[2])
 // and y3) are read twice. CPT = 2 (one access per pair) when the row length
 // is even, else 1.
 template <typename DT, int CPT>
-__device__ __forceinline__ double sweep_b_strips(const CubeArgs<DT> &a, const DevScalars *sc, int lb)
+__device__ __forceinline__ double sweep_b_strips(const CubeArgs<DT> &a, const DevScalars *sc, int lb,
+                                                 double ts, double tt)
 {
     const Dims d = a.c.d;
     const int n1 = d.n1, n2 = d.n2, n3 = d.n3;
     const int par = (int)(sc->iter & 1u);
     const Side<DT> src = a.side[par], dst = a.side[par ^ 1];
     const float a4 = (float)sc->a4;
-    const double ts = sc->sel[0].tau, tt = sc->sel[1].tau;
     double r2 = 0.0;
     const uint32_t nstrip = (uint32_t)((n1 + RB - 1) / RB);
     const uint32_t ncol = (uint32_t)(n2 / CPT);
@@ -737,10 +665,13 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh
     __syncthreads();
     const CubeArgs<DT> &a = cubes[__builtin_amdgcn_readfirstlane(cube_of_block)];
     const DevScalars *sc = a.c.sc;
-    if (idle(sc) || !(sc->sel[0].done && sc->sel[1].done)) return;
+    if (idle(sc)) return;
+    // a missed window's threshold comes from this slot's histogram passes
+    const double ts = sc->sel[0].done ? sc->sel[0].tau : fb_final(a.c.rec, 0).tau;
+    const double tt = sc->sel[1].done ? sc->sel[1].tau : fb_final(a.c.rec, 1).tau;
     const int lb = (int)blockIdx.x - a.c.b0;  // block within the cube
-    const double r2 = sweep_b_cpt(a.c.d.n2) == 2 ? sweep_b_strips<DT, 2>(a, sc, lb)
-                                                  : sweep_b_strips<DT, 1>(a, sc, lb);
+    const double r2 = sweep_b_cpt(a.c.d.n2) == 2 ? sweep_b_strips<DT, 2>(a, sc, lb, ts, tt)
+                                                  : sweep_b_strips<DT, 1>(a, sc, lb, ts, tt);
     const double tot = block_sum<NPT>(r2, red);
     if (threadIdx.x == 0) a.c.part[2 * a.c.ntiles + lb] = tot;
 }
@@ -759,15 +690,31 @@ __global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
     const double *part = cc.part;
     const int grid_a = cc.ntiles, blocks_b = cc.nb;
     __shared__ double red[3 * (NPT / 64)];
-    // the partials are read together with the flags that may make them moot
-    const bool skip = idle(sc) || !(sc->sel[0].done && sc->sel[1].done);
+    // the partials are read together with the flag that may make them moot
+    const bool skip = idle(sc);
     double du2 = 0.0, u2 = 0.0, r2 = 0.0;
     for (int b = threadIdx.x; b < grid_a; b += NPT) {
         du2 += part[2 * b];
         u2 += part[2 * b + 1];
     }
     for (int b = threadIdx.x; b < blocks_b; b += NPT) r2 += part[2 * grid_a + b];
+    if (blockIdx.x == 0 && threadIdx.x == 0) *slot_flags(table, (int)gridDim.x) = 0u;
     if (skip) return;
+    // a threshold found by this slot's histogram passes becomes the field's
+    // search state, with the window of the next iteration sized by the
+    // density of |z| around it (only this block writes the cube's state)
+    if (threadIdx.x == 0)
+        for (int f = 0; f < 2; ++f)
+            if (!sc->sel[f].done) {
+                const FbRec &r = fb_final(cc.rec, f);
+                SelState o = sc->sel[f];
+                o.tau = r.tau;
+                o.done = 1u;
+                o.full = 0u;
+                o.dens = cc.rec[f].dens;
+                set_window(o, true, window_budget(cc.d.plane));
+                sc->sel[f] = o;
+            }
     // the three block sums at once, in the order of block_sum: a butterfly
     // within each wavefront, then the wavefronts in order (thread 0)
     du2 = wave_sum(du2);
@@ -999,6 +946,7 @@ void cube_entry_t(CubeArgs<DT> *a, const Dims &d, const float *v, void *ws, cons
     c.part = (double *)(b + L.partials);
     c.winpart = (double *)(b + L.winpart);
     c.hist = (Hist *)(b + L.hist);
+    c.rec = (FbRec *)(b + L.rec);
     c.cand = (float *)(b + L.cand);
     c.ccount = (uint32_t *)(b + L.ccount);
     const int shape = tile_shape(d.n1, d.n2, (int)sizeof(DT));
@@ -1050,6 +998,8 @@ hipError_t slot_t(const void *table, const LaunchShape &sh, hipStream_t st, hipE
             hipLaunchKernelGGL((k_sweep_a<DT, 1>), dim3(sh.shape_grid[1]), dim3(NT), 0, st, cubes, sh);
     if (nev >= 2) (void)hipEventRecord(ev[1], st);
     hipError_t e = launch_select_window(table, stride, sh.ncubes, kPrefetchBlocks, st);
+    for (int level = 0; level < 3 && e == hipSuccess; ++level)
+        e = launch_fallback(table, (int)sizeof(DT), sh, level, st);
     if (e != hipSuccess) return e;
     if (nev >= 4) (void)hipEventRecord(ev[2], st);
     hipLaunchKernelGGL(k_sweep_b<DT>, dim3(sh.total_b), dim3(NPT), 0, st, cubes, sh);
