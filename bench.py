@@ -61,8 +61,12 @@ def parse():
                          "on cubes of its two image shapes, omega sweep, MPSNR/MSSIM; realshape: "
                          "the shapes and fixed radii of its real-image experiment, solved to "
                          "tol 1e-5")
-    ap.add_argument("--requests", type=int, default=40, help="serve: requests in the stream")
-    ap.add_argument("--rate", type=float, default=4.0, help="serve: Poisson arrivals per second")
+    ap.add_argument("--requests", type=int, default=0,
+                    help="serve: requests in the stream (0: those arriving within --seconds)")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: Poisson arrivals per second")
+    ap.add_argument("--seconds", type=float, default=120.0,
+                    help="serve: arrivals stop after this many seconds; the queue then drains")
+    ap.add_argument("--pool", type=int, default=4, help="serve: distinct cubes per size")
     ap.add_argument("--hbm-budget-gb", type=float, default=96.0, help="serve: admission budget")
     ap.add_argument("--active-mvoxels", type=float, default=16.0,
                     help="serve: admit while fewer voxels than this (millions) are in flight; "
@@ -342,32 +346,70 @@ def bench_batch(args):
 
 
 def bench_serve(args):
-    """A request stream (Poisson arrivals, four cube sizes, tolerance 1e-4,
-    cap 5000) served in real time by the request loop: latency from arrival
-    to result on the host, throughput, and the offered load."""
+    """A request stream (Poisson arrivals at --rate per second for --seconds,
+    four cube sizes, tolerance 1e-4, cap 5000) served in real time by the
+    request loop, then drained: latency from arrival to result on the host,
+    throughput and the offered load (rho). The same jobs are then solved one
+    after another alone (copy in, init, iterate to the rule, copy out) for
+    the rate the loop has to beat. Request q takes its cube from a pool of
+    --pool cubes per size (generating thousands of distinct cubes would take
+    the host longer than serving them); each request is still a job of its
+    own, solved from its initial point in its own workspace."""
     import numpy as np
     import torch
 
     import paper_2510_00562_amd as geo
     from paper_2510_00562_amd.serve import Job, run_stream
-    from synth.cubes import make_cube, serving_specs
+    from synth.cubes import like, make_cube, serving_specs
 
     store = geo.GEO_STORE_BF16 if args.dual == "bf16" else geo.GEO_STORE_F32
+    n_req = args.requests if args.requests > 0 else int(round(args.rate * args.seconds * 1.2)) + 8
+    specs = [(t, sp) for t, sp in serving_specs(n_req, args.rate) if t <= args.seconds]
+    pool = {}
     jobs = []
-    for q, (arr, spec) in enumerate(serving_specs(args.requests, args.rate)):
-        c = make_cube(spec)
-        jobs.append(Job(q, np.ascontiguousarray(c["v"], dtype=np.float32), c["eps"], c["alpha"],
-                        c["beta"], omega=c["omega"], tol=1e-4, cap=5000, arrival=arr))
+    for q, (arr, spec) in enumerate(specs):
+        key = (spec.n1, spec.n2, spec.n3, q % args.pool)
+        if key not in pool:
+            c = make_cube(like(spec, seed=40000 + len(pool)))
+            pool[key] = (np.ascontiguousarray(c["v"], dtype=np.float32), c["eps"], c["alpha"],
+                         c["beta"], c["omega"])
+        v, eps, alpha, beta, omega = pool[key]
+        jobs.append(Job(q, v, eps, alpha, beta, omega=omega, tol=1e-4, cap=5000, arrival=arr))
+    print(f"serve: {len(jobs)} requests in {args.seconds:.0f} s at {args.rate}/s, "
+          f"{len(pool)} distinct cubes", flush=True)
     torch.cuda.synchronize()
     cap = int(args.active_mvoxels * 1e6) if args.active_mvoxels > 0 else None
     rep = run_stream(jobs, int(args.hbm_budget_gb * 2 ** 30), round_iters=25, dual_storage=store,
                      active_voxels=cap)
     done = rep.pop("jobs")
+    print(f"serve: stream done in {rep['span_s']:.1f} s", flush=True)
     mean_vox = float(np.mean([j.v.size for j in done]))
     offered = args.rate * mean_vox * rep["mean_iterations"]
-    # the rate one GPU sustains at the throughput the loop reached: requests
-    # per second whose work (mean voxels x mean iterations) it can absorb
-    sustainable = rep["voxel_iterations_per_s"] / (mean_vox * rep["mean_iterations"])
+    sustainable = rep["busy_voxel_iterations_per_s"] / (mean_vox * rep["mean_iterations"])
+    # the same jobs alone, one after another: every distinct cube once, each
+    # weighted by how many requests used it
+    solo_t, solo_vi = 0.0, 0.0
+    uses = {}
+    for j in done:
+        uses.setdefault(id(j.v), [j, 0])[1] += 1
+    for j, k in uses.values():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        vd = torch.from_numpy(j.v).cuda()
+        dims = geo.dims_of(vd.shape)
+        p = geo.params(j.eps, j.alpha, j.beta, omega=j.omega, tol=j.tol, max_iter=j.cap,
+                       dual_storage=store)
+        ws = geo.Workspace(geo.geo_workspace_size(dims, p))
+        u, s_, t_ = (torch.empty_like(vd) for _ in range(3))
+        r = geo.geo_solve(dims, p, vd, u, s_, t_, ws)
+        host = [x.cpu() for x in (u, s_, t_)]
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        assert r.iters == j.iters, (r.iters, j.iters)
+        solo_t += k * el
+        solo_vi += k * r.iters * vd.numel()
+        del host, ws
+    solo_rate = solo_vi / solo_t
     out = {
         "metric": "P-PDS request loop latency",
         "value": rep["latency_p50_s"],
@@ -375,22 +417,28 @@ def bench_serve(args):
         "n_gpus": 1,
         "higher_is_better": False,
         "data": "synthetic",
-        "config": {"workload": f"{args.requests} requests, Poisson {args.rate}/s, sizes 128x128x64 / "
-                               "256x256x128 / 256x256x190 / 512x512x224 (0.4/0.3/0.2/0.1), "
-                               "tol 1e-4, cap 5000, FIFO admission by HBM footprint",
+        "config": {"workload": f"Poisson {args.rate}/s for {args.seconds:.0f} s ({len(done)} requests), "
+                               "sizes 128x128x64 / 256x256x128 / 256x256x190 / 512x512x224 "
+                               "(0.4/0.3/0.2/0.1), tol 1e-4, cap 5000, FIFO admission by HBM "
+                               "footprint, copies overlapped with the rounds",
                    "hbm_budget_gb": args.hbm_budget_gb, "active_mvoxels": args.active_mvoxels,
-                   "dual_storage": args.dual},
+                   "dual_storage": args.dual, "cube_pool_per_size": args.pool},
         "latency_p50_s": rep["latency_p50_s"],
         "latency_p99_s": rep["latency_p99_s"],
         "latency_mean_s": rep["latency_mean_s"],
         "requests_per_s": rep["requests_per_s"],
         "voxel_iterations_per_s": rep["voxel_iterations_per_s"],
+        "busy_voxel_iterations_per_s": rep["busy_voxel_iterations_per_s"],
+        "solo_voxel_iterations_per_s": solo_rate,
+        "served_over_solo": rep["busy_voxel_iterations_per_s"] / solo_rate,
         "mean_iterations": rep["mean_iterations"],
         "converged": rep["converged"],
+        "errors": rep["errors"],
         "offered_voxel_iterations_per_s": offered,
-        "rho": offered / rep["voxel_iterations_per_s"],
+        "rho": offered / rep["busy_voxel_iterations_per_s"],
         "sustainable_requests_per_s": sustainable,
         "span_s": rep["span_s"],
+        "busy_s": rep["busy_s"],
     }
     print(json.dumps(out), flush=True)
 

@@ -109,6 +109,8 @@ typedef struct {
     int32_t slots;       /* launch slots the call issued (one iteration of
                             every working cube each; a missed window is
                             resolved inside its slot)                       */
+    int32_t status;      /* this cube's own status: GEO_OK, GEO_MAXITER or
+                            GEO_ENONFINITE (a batch returns the worst)      */
 } geo_result;
 
 /* Workspace of a solver state for one cube (bytes, 256-byte aligned base

@@ -26,6 +26,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "libgeosstv.so")
 
 GEO_OK, GEO_MAXITER = 0, 1
+GEO_EINVAL, GEO_EWORKSPACE, GEO_EHIP, GEO_ENONFINITE = -1, -2, -3, -4
 GEO_STORE_F32, GEO_STORE_BF16 = 0, 1
 OPS = dict(dv=0, dh=1, ds=2, d=3, dds=4, l_ud=5, l_lr=6, l_c=7, l=8, k=9)
 OP_PLANES = dict(dv=(1, 1), dh=(1, 1), ds=(1, 1), d=(1, 2), dds=(1, 2), l_ud=(2, 2),
@@ -52,7 +53,7 @@ class geo_result(ctypes.Structure):
                 ("tau_s", ctypes.c_double), ("tau_t", ctypes.c_double),
                 ("total_iters", ctypes.c_int32), ("fallback_passes", ctypes.c_int32),
                 ("cand_s", ctypes.c_int32), ("cand_t", ctypes.c_int32),
-                ("slots", ctypes.c_int32)]
+                ("slots", ctypes.c_int32), ("status", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -270,11 +271,13 @@ def geo_sweep_blocks(dual_storage: int = GEO_STORE_F32) -> int:
 
 
 def geo_batch_step(dims, ps, vs, wss, table: Workspace, n_iter: int, use_graph=False,
-                   stream=None):
+                   stream=None, raise_nonfinite=True):
     """n_iter iterations of every cube of a batch in one launch sequence per
     iteration. dims, ps, vs, wss: lists (geo_dims, geo_params, device cube,
     Workspace) of equal length; table: a Workspace of geo_batch_table_size
-    bytes. Returns (status, [geo_result per cube])."""
+    bytes. Returns (status, [geo_result per cube]). raise_nonfinite=False
+    returns GEO_ENONFINITE with the results (each cube's own status in
+    .status) instead of raising."""
     n = len(dims)
     if not (len(ps) == len(vs) == len(wss) == n):
         raise ValueError("dims, ps, vs and wss must have one entry per cube")
@@ -284,9 +287,10 @@ def geo_batch_step(dims, ps, vs, wss, table: Workspace, n_iter: int, use_graph=F
     W = (_vp * n)(*[w.ptr for w in wss])
     B = (_sz * n)(*[w.nbytes for w in wss])
     out = (geo_result * n)()
-    rc = _check(lib().geo_batch_step(n, D, Pa, V, W, B, table.ptr, table.nbytes, int(n_iter),
-                                     1 if use_graph else 0, _stream(stream), out),
-                "geo_batch_step", allow_maxiter=True)
+    rc = lib().geo_batch_step(n, D, Pa, V, W, B, table.ptr, table.nbytes, int(n_iter),
+                              1 if use_graph else 0, _stream(stream), out)
+    if not (rc == GEO_ENONFINITE and not raise_nonfinite):
+        rc = _check(rc, "geo_batch_step", allow_maxiter=True)
     return rc, list(out)
 
 

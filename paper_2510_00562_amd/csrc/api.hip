@@ -370,8 +370,10 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
             o.cand_t = (int32_t)x.sel[1].cand_count;
             o.slots = (int32_t)slots;
         }
-        if (x.nonfinite) status = GEO_ENONFINITE;
-        else if (status == GEO_OK && p[c].tol > 0.0 && !x.stop) status = GEO_MAXITER;
+        const int own = x.nonfinite ? GEO_ENONFINITE : (p[c].tol > 0.0 && !x.stop ? GEO_MAXITER : GEO_OK);
+        if (out) out[c].status = own;
+        if (own == GEO_ENONFINITE) status = GEO_ENONFINITE;
+        else if (status == GEO_OK && own == GEO_MAXITER) status = GEO_MAXITER;
     }
     return status;
 }

@@ -17,7 +17,7 @@ class _Dev:
 
 
 class _FakeActive:
-    def __init__(self, job, dual_storage):
+    def __init__(self, job, dual_storage, copy=None, pinned=None):
         self.job = job
         self.vd = _Dev(job.v.shape)
         self.done = 0
