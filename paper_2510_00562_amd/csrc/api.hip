@@ -169,6 +169,12 @@ int read_scalars(const void *ws, const Layout &L, DevScalars *out, hipStream_t s
 
 }  // namespace
 
+namespace geo {
+// For entry points in other files: the status of a HIP call, keeping the
+// error for geo_strerror.
+int geo_hip_status(hipError_t e) { return hip_status(e); }
+}  // namespace geo
+
 extern "C" {
 
 const char *geo_strerror(int status)

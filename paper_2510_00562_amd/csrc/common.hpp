@@ -66,38 +66,23 @@ __device__ __forceinline__ void st2(bf16x2 *p, float2 x)
 // Stores of results this launch does not read again: with the nontemporal
 // hint their lines leave the L2 early and do not push out the halo lines
 // that neighbouring tiles still read.
-#ifndef GEO_NT_STORES
-#define GEO_NT_STORES 1
-#endif
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ void st_nt(float *p, float x)
 {
-#if GEO_NT_STORES
     __builtin_nontemporal_store(x, p);
-#else
-    *p = x;
-#endif
 }
 __device__ __forceinline__ void st_nt(float2 *p, float2 x)
 {
-#if GEO_NT_STORES
     f32x2 v;
     v.x = x.x;
     v.y = x.y;
     __builtin_nontemporal_store(v, reinterpret_cast<f32x2 *>(p));
-#else
-    *p = x;
-#endif
 }
 __device__ __forceinline__ void st_nt(bf16 *p, float x)
 {
     bf16 b;
     st(&b, x);
-#if GEO_NT_STORES
     __builtin_nontemporal_store(b.bits, &p->bits);
-#else
-    *p = b;
-#endif
 }
 __device__ __forceinline__ void st2_nt(float2 *p, float2 x) { st_nt(p, x); }
 __device__ __forceinline__ void st2_nt(bf16x2 *p, float2 x)
@@ -106,11 +91,7 @@ __device__ __forceinline__ void st2_nt(bf16x2 *p, float2 x)
     st(&a, x.x);
     st(&b, x.y);
     const uint32_t bits = (uint32_t)a.bits | ((uint32_t)b.bits << 16);
-#if GEO_NT_STORES
     __builtin_nontemporal_store(bits, &p->bits);
-#else
-    p->bits = bits;
-#endif
 }
 
 // One component (c = 0 first, 1 second) of a stored pair, nontemporal.
@@ -118,24 +99,13 @@ __device__ __forceinline__ void st_comp_nt(float2 *p, int c, float x) { st_nt(re
 __device__ __forceinline__ void st_comp_nt(bf16x2 *p, int c, float x) { st_nt(reinterpret_cast<bf16 *>(p) + c, x); }
 
 // Loads of values no other thread or tile reads (no halo reuse).
-#ifndef GEO_NT_LOADS
-#define GEO_NT_LOADS 1
-#endif
 __device__ __forceinline__ float ld_nt(const float *p)
 {
-#if GEO_NT_LOADS
     return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
 }
 __device__ __forceinline__ float ld_nt(const bf16 *p)
 {
-#if GEO_NT_LOADS
     return __uint_as_float(((uint32_t)__builtin_nontemporal_load(&p->bits)) << 16);
-#else
-    return ld(p);
-#endif
 }
 
 struct Dims {

@@ -361,12 +361,7 @@ __device__ __forceinline__ double bin_value(unsigned long long msum, uint32_t fi
     return (double)msum * ldexp(1.0, (int)(e ? e : 1u) - 150);
 }
 
-#ifndef GEO_PREFETCH_BUDGET
-#define GEO_PREFETCH_BUDGET 96  // MB, of the 256 MB memory-side cache
-#endif
-#ifndef GEO_PREFETCH_MASK
-#define GEO_PREFETCH_MASK 31  // s, t, y3, y4, the y4 intermediate
-#endif
+constexpr double kPrefetchBudgetMB = 96.0;  // of the 256 MB memory-side cache
 // Blocks past the search's read sweep B's inputs once, so that sweep B finds
 // them in the memory-side cache (the search itself keeps only two CUs per
 // cube busy). The values are consumed by an empty asm statement only.
@@ -387,16 +382,16 @@ __device__ void prefetch_sweep_b_inputs(const char *table, int stride, int ncube
         const int c = tid / 5, a = tid % 5;
         const CubeCommon &cc = *reinterpret_cast<const CubeCommon *>(table + (size_t)c * stride);
         const DevScalars *sc = cc.sc;
-        if (((GEO_PREFETCH_MASK >> a) & 1) && !idle(sc)) {
+        if (!idle(sc)) {  // s, t, y3, y4 and the y4 intermediate
             p = reinterpret_cast<const uint4 *>(cc.bin[sc->iter & 1u][a]);
             bytes = (double)cc.bin_bytes[a];
         }
     }
-    // at most GEO_PREFETCH_BUDGET MB in all: the leading part of every
+    // at most kPrefetchBudgetMB in all: the leading part of every
     // array, which is what sweep B's first grid-stride rounds read
     double total = bytes, z1 = 0.0, z2 = 0.0;
     block_sum3(total, z1, z2, wsd);
-    const double frac = total > 0.0 ? fmin(1.0, GEO_PREFETCH_BUDGET * 1048576.0 / total) : 0.0;
+    const double frac = total > 0.0 ? fmin(1.0, kPrefetchBudgetMB * 1048576.0 / total) : 0.0;
     const uint32_t n16 = (uint32_t)(frac * (bytes / 16.0));
     uint32_t all;
     const uint32_t first = block_exclusive_scan<uint32_t>(n16, wsu, all);

@@ -113,9 +113,6 @@ struct Layout {
 //     outside the cube (N2 = 160: 37.5% of the lanes of two 128-wide tiles,
 //     17% of three 64-wide ones). Idle lanes cost time, since the sweep's
 //     rate is set by its loads in flight.
-#ifndef GEO_SWEEP_B_ROWS
-#define GEO_SWEEP_B_ROWS 2
-#endif
 constexpr int kTileShapes = 2;
 constexpr int kShapeTI[kTileShapes] = {8, 16}, kShapeTJ[kTileShapes] = {128, 64};
 constexpr int kSweepThreads = 1024;
@@ -124,10 +121,8 @@ constexpr int kMinKC = 8;
 constexpr int kMaxTiles = 4096;      // tiles of one cube (slices of its search)
 constexpr int kMaxBatch = 64;        // cubes of one batched launch
 constexpr int kPointThreads = 256;
-#ifndef GEO_SWEEP_B_BLOCKS
-#define GEO_SWEEP_B_BLOCKS 2048
-#endif
-constexpr int kSweepBBlocks = GEO_SWEEP_B_BLOCKS;  // grid-stride blocks of sweep B per cube
+constexpr int kSweepBBlocks = 2048;  // grid-stride blocks of sweep B per cube
+constexpr int kSweepBRows = 2;       // rows of a sweep B strip
 constexpr int kTimedEvery = 8;  // geo_step_timed: events around every 8th sweep A
 
 inline int ceil_div(int64_t a, int64_t b) { return (int)((a + b - 1) / b); }
@@ -393,6 +388,10 @@ hipError_t launch_select_window(const void *table, int stride, int ncubes, int p
 int fallback_grid();
 hipError_t launch_fallback(const void *table, int dual_bytes, const LaunchShape &sh, int level,
                            hipStream_t st);
+
+// GEO_OK for hipSuccess, else GEO_EHIP with the error kept for
+// geo_strerror (api.hip).
+int geo_hip_status(hipError_t e);
 
 // Standalone projections (ops.hip).
 int l2_blocks(int64_t n);

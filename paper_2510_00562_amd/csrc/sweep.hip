@@ -504,11 +504,8 @@ __device__ __forceinline__ float soft(float z, double tau)
     return m > 0.0 ? copysignf((float)m, z) : 0.0f;
 }
 
-constexpr int RB = GEO_SWEEP_B_ROWS;  // rows per sweep B strip
-#ifndef GEO_PREFETCH_BLOCKS
-#define GEO_PREFETCH_BLOCKS 240
-#endif
-constexpr int kPrefetchBlocks = GEO_PREFETCH_BLOCKS;  // cache prefetch beside the search
+constexpr int RB = kSweepBRows;  // rows per sweep B strip
+constexpr int kPrefetchBlocks = 240;  // cache prefetch beside the search
 // CPT consecutive values of one row: one 4- or 8-byte access for a pair.
 __device__ __forceinline__ void ldv(const float *p, float (&o)[1]) { o[0] = *p; }
 __device__ __forceinline__ void ldv(const bf16 *p, float (&o)[1]) { o[0] = ld(p); }
@@ -528,23 +525,15 @@ __device__ __forceinline__ void ldv_nt(const float *p, float (&o)[1]) { o[0] = l
 __device__ __forceinline__ void ldv_nt(const bf16 *p, float (&o)[1]) { o[0] = ld_nt(p); }
 __device__ __forceinline__ void ldv_nt(const float *p, float (&o)[2])
 {
-#if GEO_NT_LOADS
     const f32x2 x = __builtin_nontemporal_load(reinterpret_cast<const f32x2 *>(p));
     o[0] = x.x;
     o[1] = x.y;
-#else
-    ldv(p, o);
-#endif
 }
 __device__ __forceinline__ void ldv_nt(const bf16 *p, float (&o)[2])
 {
-#if GEO_NT_LOADS
     const uint32_t b = __builtin_nontemporal_load(reinterpret_cast<const uint32_t *>(p));
     o[0] = __uint_as_float(b << 16);
     o[1] = __uint_as_float(b & 0xffff0000u);
-#else
-    ldv(p, o);
-#endif
 }
 template <typename T>
 __device__ __forceinline__ void stv_nt(T *p, const float (&x)[1]) { st_nt(p, x[0]); }

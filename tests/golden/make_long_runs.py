@@ -15,6 +15,10 @@ Runs (pick any with their names on the command line; default: all):
   512    long_512x512x224_5000.json: the 512 x 512 x 224 cube after 5000
          iterations, the same fields at checkpoints after 1, 10, 100, 1000
          and 5000 iterations. About 5 hours on 8 cores and 31 GB of memory.
+  quality quality_cases_300.json: the paper's noise cases 1 and 5 (Sec.
+         IV-A) on a 120 x 120 x 99 synthetic cube with the radii of eqs.
+         (25)-(27), for omega 0.01, 0.03 and 0.05: 300 iterations each, the
+         same fields plus MSSIM (eq. (30)). A few minutes.
 
 Run from the repository root: python tests/golden/make_long_runs.py [runs]"""
 import json
@@ -125,7 +129,31 @@ def run_512():
                                                   complete=target == 5000))
 
 
-RUNS = {"256": run_256, "batch": run_batch, "512": run_512}
+QUALITY_CASES, QUALITY_OMEGAS, QUALITY_ITERS = (1, 5), (0.01, 0.03, 0.05), 300
+
+
+def run_quality():
+    from synth.cubes import PAVIA_SHAPE, paper_case
+    from synth.quality import mssim
+    n1, n2, n3 = PAVIA_SHAPE
+    solves = []
+    for case in QUALITY_CASES:
+        for omega in QUALITY_OMEGAS:
+            c = paper_case(case, n1, n2, n3, seed=0, omega=omega)
+            S = solver_for(c)
+            t0 = time.time()
+            run_to(S, f"case {case} omega {omega}", QUALITY_ITERS, t0, every=QUALITY_ITERS)
+            idx = sample_index(S.u.size)
+            e = {"case": case, "omega": omega, "eps": c["eps"], "alpha": c["alpha"],
+                 "beta": c["beta"], "sample_index": idx.tolist(),
+                 "mssim": mssim(S.u, c["u_clean"])}
+            e.update(snapshot(S, c["u_clean"], idx, QUALITY_ITERS))
+            solves.append(e)
+    write("quality_cases_300.json", {"shape": [n3, n1, n2], "iterations": QUALITY_ITERS,
+                                     "sample_seed": SAMPLE_SEED, "solves": solves})
+
+
+RUNS = {"256": run_256, "batch": run_batch, "512": run_512, "quality": run_quality}
 
 if __name__ == "__main__":
     for name in (sys.argv[1:] or list(RUNS)):
