@@ -271,6 +271,19 @@ int geo_project_l1_workspace_size(int64_t n, size_t *bytes);
 int geo_project_l1(const float *x, int64_t n, double radius, float *out,
                    double *tau, void *ws, size_t ws_bytes, void *stream);
 
+/* geo_project_l1 for callers that cannot allocate (code under HIP graph
+ * capture, serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and the same results, with the scratch in a fixed 32 KiB device
+ * array of the library (one per GPU, kept until the process ends) instead of
+ * a workspace. Allocates nothing, copies nothing to the host, does not
+ * synchronise. tau_dev: DEVICE pointer to one double receiving the level (0
+ * inside the ball, +inf for radius 0), or NULL. n <= 2^31 - 1, else
+ * GEO_EINVAL. Every call on a GPU uses that GPU's one scratch array: calls
+ * that overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller. */
+int geo_project_l1_noalloc(const float *x, int64_t n, double radius, float *out,
+                           double *tau_dev, void *stream);
+
 /* Projection onto the ball of radius eps around center, eq. (23). *r (host)
  * receives ||x - center||_2 (FP64). Blocking. */
 int geo_project_l2_workspace_size(int64_t n, size_t *bytes);

@@ -97,6 +97,7 @@ def lib():
             "geo_apply_op": [i32, i32, geo_dims, _vp, _vp, _vp],
             "geo_project_l1_workspace_size": [i64, ctypes.POINTER(_sz)],
             "geo_project_l1": [_vp, i64, d, _vp, ctypes.POINTER(d), _vp, _sz, _vp],
+            "geo_project_l1_noalloc": [_vp, i64, d, _vp, _vp, _vp],
             "geo_project_l2_workspace_size": [i64, ctypes.POINTER(_sz)],
             "geo_project_l2": [_vp, _vp, i64, d, _vp, ctypes.POINTER(d), _vp, _sz, _vp],
             "geo_prox_l12": [_vp, _vp, i64, d, _vp, _vp, _vp],
@@ -321,6 +322,16 @@ def geo_project_l1(x, radius: float, out, ws: Workspace | None = None, stream=No
     _check(lib().geo_project_l1(_f32(x), n, float(radius), _f32(out), ctypes.byref(tau), ws.ptr,
                                 ws.nbytes, _stream(stream)), "geo_project_l1")
     return tau.value
+
+
+def geo_project_l1_noalloc(x, radius: float, out, tau_dev=None, stream=None):
+    """geo_project_l1 with the library's fixed scratch: no allocation, no
+    host copy, no synchronisation. tau_dev: a float64 device tensor of one
+    element receiving the level, or None."""
+    n = x.numel()
+    tp = ctypes.c_void_p(tau_dev.data_ptr()) if tau_dev is not None else None
+    _check(lib().geo_project_l1_noalloc(_f32(x), n, float(radius), _f32(out), tp, _stream(stream)),
+           "geo_project_l1_noalloc")
 
 
 def geo_project_l2(x, center, eps: float, out, ws: Workspace | None = None, stream=None) -> float:
