@@ -80,6 +80,13 @@ def _setup(L):
     L.ora_step_sizes.argtypes = [_dp]
     L.ora_set_threads.argtypes = [i]
     L.ora_get_threads.restype = i
+    L.ora_var_planes.argtypes = [i]
+    L.ora_var_planes.restype = i
+    L.ora_var_step_sizes.argtypes = [i, d, _dp]
+    L.ora_var_apply_k.argtypes = [i, i, i, i, d, i, _dp, _dp]
+    L.ora_var_init.argtypes = [i, i, i, i, _dp] + [_dp] * 6
+    L.ora_var_run.argtypes = [i, i, i, ctypes.POINTER(Params), i, _dp] + [_dp] * 6 + [i, d, i, _dp]
+    L.ora_var_run.restype = i
     global _max_threads
     _max_threads = L.ora_get_threads()
 
@@ -237,6 +244,80 @@ class Solver:
         tr = np.zeros(4 * max(n, 1))
         done = lib().ora_run(*self.dims, ctypes.byref(self.params), _p(self.v), *self._ptrs(),
                              n, tol, len(self.trace), _p(tr))
+        self.trace.extend(tuple(tr[4 * q:4 * q + 4]) for q in range(done))
+        return done
+
+    def __getattr__(self, name):
+        st = self.__dict__.get("state")
+        if st is not None and name in st:
+            return st[name]
+        raise AttributeError(name)
+
+
+# The comparison regularizers of Sec. IV-A, solved by the same P-PDS.
+SSTV, HSSTV1, HSSTV2 = 1, 2, 3
+VARIANTS = {"sstv": SSTV, "hsstv1": HSSTV1, "hsstv2": HSSTV2}
+
+
+def var_planes(variant: int) -> int:
+    """Entries of A u per voxel: 2 for SSTV (D D_s u), 4 for HSSTV
+    (D D_s u and omega D u)."""
+    return lib().ora_var_planes(int(variant))
+
+
+def var_step_sizes(variant: int, omega: float):
+    """Step sizes (u, s, t, y) of a variant: eq. (8) with the operator-norm
+    bounds of D_v, D, D D_s and omega D."""
+    out = np.zeros(4)
+    lib().ora_var_step_sizes(int(variant), float(omega), _p(out))
+    return tuple(out)
+
+
+def var_apply_k(variant: int, omega: float, x, shape, adjoint: bool = False):
+    """The stacked operator of a variant's problem, (u, s, t) -> (A u, D_v t,
+    u + s + t), or its adjoint, on flat vectors."""
+    n3, n1, n2 = shape
+    N = n1 * n2 * n3
+    P = var_planes(variant)
+    x = _c(x).ravel()
+    assert x.size == ((P + 2) * N if adjoint else 3 * N)
+    out = np.empty(3 * N if adjoint else (P + 2) * N)
+    lib().ora_var_apply_k(n1, n2, n3, int(variant), float(omega), 1 if adjoint else 0, _p(x), _p(out))
+    return out
+
+
+VAR_STATE = ("u", "s", "t", "y1", "y3", "y4")
+
+
+class VariantSolver:
+    """P-PDS (eq. (7)) for problem (15) with the GeoSSTV term replaced by a
+    comparison regularizer (SSTV, HSSTV1, HSSTV2), in double precision. y1
+    holds var_planes(variant) planes."""
+
+    def __init__(self, v, eps, alpha, beta, variant, mu_lo=0.0, mu_hi=1.0, omega=0.03, state=None):
+        self.v = _c(v)
+        self.shape = self.v.shape
+        n3, n1, n2 = self.shape
+        self.dims = (n1, n2, n3)
+        self.variant = int(variant)
+        self.params = Params(eps, alpha, beta, mu_lo, mu_hi, omega)
+        P = var_planes(self.variant)
+        self.state = {n: np.zeros(((P,) if n == "y1" else ()) + self.shape) for n in VAR_STATE}
+        if state is None:
+            lib().ora_var_init(*self.dims, self.variant, _p(self.v), *self._ptrs())
+        else:
+            for n in VAR_STATE:
+                self.state[n][...] = state[n]
+        self.trace = []
+
+    def _ptrs(self):
+        return [_p(self.state[n]) for n in VAR_STATE]
+
+    def step(self, n: int = 1, tol: float = 0.0) -> int:
+        lib().ora_set_threads(threads_for(self.v.size))
+        tr = np.zeros(4 * max(n, 1))
+        done = lib().ora_var_run(*self.dims, ctypes.byref(self.params), self.variant, _p(self.v),
+                                 *self._ptrs(), n, tol, len(self.trace), _p(tr))
         self.trace.extend(tuple(tr[4 * q:4 * q + 4]) for q in range(done))
         return done
 

@@ -638,3 +638,229 @@ int ora_run(int n1, int n2, int n3, const ora_params *p, const double *v,
     free(ws);
     return it;
 }
+
+/* ------- the comparison regularizers through the same P-PDS (Sec. IV-A) -------
+ *
+ * The paper solves problem (15) with the GeoSSTV term replaced by the
+ * regularizers of its comparison methods. Their definitions come from the
+ * cited works:
+ *   SSTV (Aggarwal and Majumdar):  ||D D_s u||_1;
+ *   HSSTV (Takeyama et al.):       ||A_w u||_{1,p} with A_w u = (D D_s u, omega D u)
+ *                                  in R^{4N}; HSSTV1: p = 1, the l1 norm of all
+ *                                  4N entries; HSSTV2: p = 2, per voxel the l2
+ *                                  norm of its four entries, summed.
+ * Problem (15) with such a term is P-PDS-ready as it stands: primal blocks
+ * x = (u, s, t) with f = iota_R(u) + iota_{B1,alpha}(s) + iota_{B1,beta}(t),
+ * dual blocks z = K x = (A u, D_v t, u + s + t) with g = R_A(z1) +
+ * iota_{0}(z2) + iota_{B2,eps}^v(z3), R_A the variant's norm.
+ * Step sizes: eq. (8) with the operator-norm bounds ||D_v||^2 <= 4,
+ * ||D||^2 <= 8, ||D D_s||^2 <= 32, ||omega D||^2 <= 8 omega^2:
+ *   g_u = 1 / (||A||^2 + 1), g_s = 1, g_t = 1 / (4 + 1), g_y = 1/3 (three
+ * primal blocks). */
+
+enum { VAR_SSTV = 1, VAR_HSSTV1 = 2, VAR_HSSTV2 = 3 };
+
+/* entries of A u per voxel: 2 (SSTV) or 4 (HSSTV) */
+int ora_var_planes(int variant) { return variant == VAR_SSTV ? 2 : 4; }
+
+static double var_norm_a2(int variant, double omega)
+{
+    return variant == VAR_SSTV ? 32.0 : 32.0 + 8.0 * omega * omega;
+}
+
+/* The step sizes (u, s, t, y) of a variant, for the tests. */
+void ora_var_step_sizes(int variant, double omega, double *out)
+{
+    out[0] = 1.0 / (var_norm_a2(variant, omega) + 1.0);
+    out[1] = 1.0;
+    out[2] = 1.0 / 5.0;
+    out[3] = 1.0 / 3.0;
+}
+
+/* out = A u: planes [D_v D_s u, D_h D_s u] and, for HSSTV, [omega D_v u,
+ * omega D_h u]. tmp: N doubles. */
+static void var_apply_a(int n1, int n2, int n3, int variant, double omega, const double *u,
+                        double *out, double *tmp)
+{
+    ix N = (ix)n1 * n2 * n3;
+    ora_ds(n1, n2, n3, u, tmp);
+    ora_d(n1, n2, n3, tmp, out);
+    if (variant != VAR_SSTV) {
+        ora_d(n1, n2, n3, u, out + 2 * N);
+#pragma omp parallel for schedule(static)
+        for (ix q = 2 * N; q < 4 * N; ++q) out[q] *= omega;
+    }
+}
+
+/* out = A^T y. tmp: 3N doubles. */
+static void var_apply_at(int n1, int n2, int n3, int variant, double omega, const double *y,
+                         double *out, double *tmp)
+{
+    ix N = (ix)n1 * n2 * n3;
+    double *a = tmp, *b = tmp + N, *c = tmp + 2 * N;
+    d_t_ws(n1, n2, n3, y, a, b);
+    ora_ds_t(n1, n2, n3, a, out);
+    if (variant != VAR_SSTV) {
+        d_t_ws(n1, n2, n3, y + 2 * N, c, b);
+#pragma omp parallel for schedule(static)
+        for (ix q = 0; q < N; ++q) out[q] += omega * c[q];
+    }
+}
+
+/* The stacked operator K of a variant and its adjoint, for the tests:
+ * x = (u, s, t) (3N) -> z = (A u, D_v t, u + s + t) ((P + 2) N, P planes of
+ * A u); adjoint = 1 maps z back. */
+void ora_var_apply_k(int n1, int n2, int n3, int variant, double omega, int adjoint,
+                     const double *in, double *out)
+{
+    ix N = (ix)n1 * n2 * n3;
+    const int P = ora_var_planes(variant);
+    double *tmp = (double *)malloc(sizeof(double) * 3 * N);
+    if (!adjoint) {
+        const double *u = in, *s = in + N, *t = in + 2 * N;
+        var_apply_a(n1, n2, n3, variant, omega, u, out, tmp);
+        ora_dv(n1, n2, n3, t, out + P * N);
+        double *z3 = out + (P + 1) * N;
+#pragma omp parallel for schedule(static)
+        for (ix q = 0; q < N; ++q) z3[q] = u[q] + s[q] + t[q];
+    } else {
+        const double *y1 = in, *y3 = in + P * N, *y4 = in + (P + 1) * N;
+        double *gu = out, *gs = out + N, *gt = out + 2 * N;
+        var_apply_at(n1, n2, n3, variant, omega, y1, gu, tmp);
+        ora_dv_t(n1, n2, n3, y3, gt);
+#pragma omp parallel for schedule(static)
+        for (ix q = 0; q < N; ++q) {
+            gu[q] += y4[q];
+            gs[q] = y4[q];
+            gt[q] += y4[q];
+        }
+    }
+    free(tmp);
+}
+
+/* prox of g_y R_A^* on the first dual block, by the Moreau decomposition (3):
+ * prox_{G R*}(z) = z - G prox_{R/G}(z/G). For the l1 norm prox_{R/G} is the
+ * soft threshold at 1/G, which leaves the clip of z to [-1, 1]; for the
+ * l1,2 norm over 4-entry groups it is the group shrink at 1/G, which leaves
+ * each group scaled into the unit l2 ball. */
+static void var_prox_dual(int variant, ix N, double *y)
+{
+    if (variant != VAR_HSSTV2) {
+#pragma omp parallel for schedule(static)
+        for (ix q = 0; q < ora_var_planes(variant) * N; ++q) y[q] = y[q] < -1.0 ? -1.0 : (y[q] > 1.0 ? 1.0 : y[q]);
+        return;
+    }
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) {
+        double nr = 0.0;
+        for (int g = 0; g < 4; ++g) nr += y[g * N + q] * y[g * N + q];
+        nr = sqrt(nr);
+        if (nr > 1.0)
+            for (int g = 0; g < 4; ++g) y[g * N + q] /= nr;
+    }
+}
+
+/* Initial point: u = v, s = t = 0, every dual zero. y1: P planes. */
+void ora_var_init(int n1, int n2, int n3, int variant, const double *v, double *u, double *s,
+                  double *t, double *y1, double *y3, double *y4)
+{
+    ix N = (ix)n1 * n2 * n3;
+    memcpy(u, v, sizeof(double) * N);
+    memset(s, 0, sizeof(double) * N);
+    memset(t, 0, sizeof(double) * N);
+    memset(y1, 0, sizeof(double) * ora_var_planes(variant) * N);
+    memset(y3, 0, sizeof(double) * N);
+    memset(y4, 0, sizeof(double) * N);
+}
+
+/* One P-PDS iteration, eq. (7), for a variant:
+ *   x+ = prox_{T f}(x - T K^T y),  x' = 2 x+ - x,  y+ = prox_{Sigma g*}(y + Sigma K x').
+ * trace as for ora_step. ws: (P + 12) N doubles. */
+static void var_step_ws(int n1, int n2, int n3, const ora_params *p, int variant, const double *v,
+                        double *u, double *s, double *t, double *y1, double *y3, double *y4,
+                        double *trace, double *ws)
+{
+    ix N = (ix)n1 * n2 * n3;
+    const int P = ora_var_planes(variant);
+    double st[4];
+    ora_var_step_sizes(variant, p->omega, st);
+    const double gu = st[0], gs = st[1], gt = st[2], gy = st[3];
+    double *un = ws, *sn = ws + N, *tn = ws + 2 * N, *ga = ws + 3 * N, *gb = ws + 4 * N;
+    double *z1 = ws + 5 * N, *tmp = ws + (5 + P) * N; /* tmp: 7N */
+
+    /* primal half: forward step with K^T y, then the block proxes */
+    var_apply_at(n1, n2, n3, variant, p->omega, y1, ga, tmp);
+    ora_dv_t(n1, n2, n3, y3, gb);
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) {
+        un[q] = u[q] - gu * (ga[q] + y4[q]);
+        sn[q] = s[q] - gs * y4[q];
+        tn[q] = t[q] - gt * (gb[q] + y4[q]);
+    }
+    ora_proj_box(un, N, p->mu_lo, p->mu_hi, un);
+    const double tau_s = ora_proj_l1(sn, N, p->alpha, sn);
+    const double tau_t = ora_proj_l1(tn, N, p->beta, tn);
+
+    /* extrapolated point x' = 2 x+ - x (into ga, gb, tmp) */
+    double *up = ga, *sp = gb, *tp = tmp + 3 * N;
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) {
+        up[q] = 2.0 * un[q] - u[q];
+        sp[q] = 2.0 * sn[q] - s[q];
+        tp[q] = 2.0 * tn[q] - t[q];
+    }
+
+    /* dual half: forward step with K x', then the conjugate proxes */
+    var_apply_a(n1, n2, n3, variant, p->omega, up, z1, tmp);
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < P * N; ++q) y1[q] += gy * z1[q];
+    var_prox_dual(variant, N, y1);
+    ora_dv(n1, n2, n3, tp, tmp);
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) {
+        y3[q] += gy * tmp[q];
+        y4[q] += gy * (up[q] + sp[q] + tp[q]);
+    }
+    /* the l2-ball block, as for GeoSSTV: y4 - g_y P_B(y4 / g_y) */
+    double *a = tmp, *b = tmp + N;
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) a[q] = y4[q] / gy;
+    const double r = ora_proj_l2(a, v, N, p->eps, b);
+#pragma omp parallel for schedule(static)
+    for (ix q = 0; q < N; ++q) y4[q] = y4[q] - gy * b[q];
+
+    double dn = 0.0, un2 = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : dn, un2)
+    for (ix q = 0; q < N; ++q) {
+        dn += (un[q] - u[q]) * (un[q] - u[q]);
+        un2 += u[q] * u[q];
+    }
+    memcpy(u, un, sizeof(double) * N);
+    memcpy(s, sn, sizeof(double) * N);
+    memcpy(t, tn, sizeof(double) * N);
+    if (trace) {
+        trace[0] = un2 > 0.0 ? sqrt(dn) / sqrt(un2) : INFINITY;
+        trace[1] = r;
+        trace[2] = tau_s;
+        trace[3] = tau_t;
+    }
+}
+
+/* As ora_run, for a variant (same stopping rule and trace). */
+int ora_var_run(int n1, int n2, int n3, const ora_params *p, int variant, const double *v,
+                double *u, double *s, double *t, double *y1, double *y3, double *y4,
+                int max_iter, double tol, int done_before, double *trace_all)
+{
+    double tr[4];
+    int it = 0;
+    const int P = ora_var_planes(variant);
+    double *ws = (double *)malloc(sizeof(double) * (ix)(P + 12) * n1 * n2 * n3);
+    while (it < max_iter) {
+        var_step_ws(n1, n2, n3, p, variant, v, u, s, t, y1, y3, y4, tr, ws);
+        if (trace_all) memcpy(trace_all + 4 * it, tr, sizeof tr);
+        ++it;
+        if (tol > 0.0 && done_before + it >= 2 && tr[0] < tol) break;
+    }
+    free(ws);
+    return it;
+}
