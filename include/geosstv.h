@@ -92,7 +92,33 @@ typedef struct {
                             than 4096 tiles). A performance knob only:
                             results do not depend on it beyond FP64
                             summation order.                              */
+    int32_t regularizer; /* GEO_REG_GEOSSTV (0, the method of the paper) or
+                            one of the regularizers it compares against
+                            (Sec. IV-A), in the same constrained problem
+                            (15) and solved by the same P-PDS (eq. (7)):
+                              GEO_REG_SSTV    ||D D_s u||_1
+                              GEO_REG_HSSTV1  ||(D D_s u, omega D u)||_1
+                              GEO_REG_HSSTV2  sum over voxels of the l2
+                                              norm of the 4 entries of
+                                              (D D_s u, omega D u) there
+                            with step sizes from eq. (8) and the operator
+                            norm bounds ||D D_s||^2 <= 32, ||omega D||^2
+                            <= 8 omega^2, ||D_v||^2 <= 4: u 1/33 (SSTV) or
+                            1/(33 + 8 omega^2), s 1, t 1/5, duals 1/3. The
+                            variants take GEO_STORE_F32 only, geo_workspace_
+                            size, geo_state_init/get/set, geo_step and
+                            geo_solve (not the batched, timed or profiled
+                            entry points: GEO_EINVAL), and any dims with
+                            N < 2^31. Their state: u, s, t, y1 (2 planes
+                            [D_v D_s u, D_h D_s u] for SSTV, 4 for HSSTV
+                            with [omega D_v u, omega D_h u] after them), y3
+                            (D_v t) and y4 (u + s + t); w1, w2 and y2 do
+                            not exist (GEO_EINVAL). The geo_result fields
+                            fallback_passes, cand_s, cand_t are 0 and slots
+                            counts iterations.                            */
 } geo_params;
+
+enum { GEO_REG_GEOSSTV = 0, GEO_REG_SSTV = 1, GEO_REG_HSSTV1 = 2, GEO_REG_HSSTV2 = 3 };
 
 typedef struct {
     int32_t iters;       /* iterations performed by this call               */

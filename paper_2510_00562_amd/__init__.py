@@ -19,7 +19,8 @@ __all__ = [
     "geo_dims", "geo_params", "geo_result", "GeoError", "lib", "library_path",
     "geo_workspace_size", "geo_state_init", "geo_step", "geo_step_profiled", "geo_solve", "geo_state_get",
     "geo_state_set", "geo_apply_op", "geo_project_l1", "geo_project_l2", "geo_prox_l12",
-    "geo_project_box", "geo_strerror", "OPS", "VARS", "VAR_PLANES", "Workspace",
+    "geo_project_box", "geo_strerror", "OPS", "VARS", "VAR_PLANES", "REGULARIZERS", "var_planes",
+    "Workspace",
 ]
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -33,6 +34,18 @@ OP_PLANES = dict(dv=(1, 1), dh=(1, 1), ds=(1, 1), d=(1, 2), dds=(1, 2), l_ud=(2,
                  l_lr=(2, 2), l_c=(2, 2), l=(2, 6), k=(15, 6))
 VARS = dict(u=0, s=1, t=2, w1=3, w2=4, y1=5, y2=6, y3=7, y4=8)
 VAR_PLANES = dict(u=1, s=1, t=1, w1=6, w2=6, y1=2, y2=2, y3=1, y4=1)
+# the comparison regularizers of Sec. IV-A (GEO_REG_*); 0 is GeoSSTV
+REGULARIZERS = dict(geosstv=0, sstv=1, hsstv1=2, hsstv2=3)
+
+
+def var_planes(var: str, regularizer: int = 0) -> int:
+    """Planes of a state variable: y1 has 2 (SSTV) or 4 (HSSTV1/2) planes
+    for the comparison regularizers, which have no w1, w2 or y2."""
+    if regularizer and var in ("w1", "w2", "y2"):
+        raise KeyError(f"{var} does not exist for regularizer {regularizer}")
+    if regularizer and var == "y1":
+        return 2 if regularizer == REGULARIZERS["sstv"] else 4
+    return VAR_PLANES[var]
 
 
 class geo_dims(ctypes.Structure):
@@ -44,7 +57,8 @@ class geo_params(ctypes.Structure):
                 ("mu_lo", ctypes.c_double), ("mu_hi", ctypes.c_double),
                 ("omega", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("tol", ctypes.c_double), ("dual_storage", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("band_chunk", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("band_chunk", ctypes.c_int32),
+                ("regularizer", ctypes.c_int32)]
 
 
 class geo_result(ctypes.Structure):
@@ -159,9 +173,12 @@ def dims_of(shape) -> geo_dims:
 
 
 def params(eps, alpha, beta, mu_lo=0.0, mu_hi=1.0, omega=0.03, max_iter=1000, tol=0.0,
-           dual_storage=GEO_STORE_F32, check_every=0, band_chunk=0) -> geo_params:
+           dual_storage=GEO_STORE_F32, check_every=0, band_chunk=0, regularizer=0) -> geo_params:
+    """regularizer: 0 (GeoSSTV), a GEO_REG_* value or a name of REGULARIZERS."""
+    if isinstance(regularizer, str):
+        regularizer = REGULARIZERS[regularizer]
     return geo_params(eps, alpha, beta, mu_lo, mu_hi, omega, max_iter, tol, dual_storage,
-                      check_every, band_chunk)
+                      check_every, band_chunk, regularizer)
 
 
 def _check(rc, where, allow_maxiter=False):

@@ -137,8 +137,12 @@ bool params_ok(const geo_params *p)
     if (p->dual_storage != GEO_STORE_F32 && p->dual_storage != GEO_STORE_BF16) return false;
     if (p->check_every < 0) return false;
     if (p->band_chunk < 0) return false;
+    if (p->regularizer < GEO_REG_GEOSSTV || p->regularizer > GEO_REG_HSSTV2) return false;
+    if (p->regularizer != GEO_REG_GEOSSTV && p->dual_storage != GEO_STORE_F32) return false;
     return true;
 }
+
+bool is_variant(const geo_params *p) { return p && p->regularizer != GEO_REG_GEOSSTV; }
 
 Dims to_dims(geo_dims d)
 {
@@ -158,6 +162,39 @@ int check_ws(geo_dims d, const geo_params *p, const void *ws, size_t ws_bytes, L
 }
 
 hipStream_t S(void *stream) { return (hipStream_t)stream; }
+
+// The comparison regularizers (variants.hip): any dims with N < 2^31.
+int check_var_ws(geo_dims d, const geo_params *p, const void *ws, size_t ws_bytes)
+{
+    if (!ws || ((uintptr_t)ws & 255u) || ws_bytes < var_workspace_bytes(d.n1, d.n2, d.n3, p->regularizer))
+        return GEO_EWORKSPACE;
+    return GEO_OK;
+}
+
+int var_step_impl(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
+                  int32_t n_iter, hipStream_t st, geo_result *out)
+{
+    int rc = check_var_ws(dims, p, ws, ws_bytes);
+    if (rc) return rc;
+    VarScalars x;
+    double ts = 0.0, tt = 0.0;
+    rc = hip_status(var_step(to_dims(dims), p, v, ws, n_iter, st, &x, &ts, &tt));
+    if (rc) return rc;
+    const int own = x.nonfinite ? GEO_ENONFINITE : (p->tol > 0.0 && !x.stop ? GEO_MAXITER : GEO_OK);
+    if (out) {
+        memset(out, 0, sizeof *out);
+        out->iters = (int32_t)x.calls_iter;
+        out->converged = (p->tol > 0.0 && x.stop && !x.nonfinite) ? 1 : 0;
+        out->rel_change = x.rel;
+        out->r = x.r;
+        out->tau_s = ts;
+        out->tau_t = tt;
+        out->total_iters = (int32_t)x.iter;
+        out->slots = (int32_t)x.calls_iter;
+        out->status = own;
+    }
+    return own;
+}
 
 int read_scalars(const void *ws, const Layout &L, DevScalars *out, hipStream_t st)
 {
@@ -192,6 +229,11 @@ const char *geo_strerror(int status)
 
 int geo_workspace_size(geo_dims dims, const geo_params *p, size_t *bytes)
 {
+    if (is_variant(p)) {
+        if (!dims_ok(dims) || !bytes || !params_ok(p)) return GEO_EINVAL;
+        *bytes = var_workspace_bytes(dims.n1, dims.n2, dims.n3, p->regularizer);
+        return GEO_OK;
+    }
     if (!solver_dims_ok(dims) || !bytes) return GEO_EINVAL;
     if (p && (p->dual_storage != GEO_STORE_F32 && p->dual_storage != GEO_STORE_BF16))
         return GEO_EINVAL;
@@ -202,6 +244,11 @@ int geo_workspace_size(geo_dims dims, const geo_params *p, size_t *bytes)
 int geo_state_init(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
                    void *stream)
 {
+    if (is_variant(p)) {
+        if (!dims_ok(dims) || !params_ok(p) || !v) return GEO_EINVAL;
+        const int rc = check_var_ws(dims, p, ws, ws_bytes);
+        return rc ? rc : hip_status(var_state_init(to_dims(dims), p, v, ws, S(stream)));
+    }
     if (!solver_dims_ok(dims) || !params_ok(p) || !v) return GEO_EINVAL;
     Layout L;
     int rc = check_ws(dims, p, ws, ws_bytes, &L);
@@ -233,7 +280,7 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         return GEO_EINVAL;
     std::vector<Layout> L(n);
     for (int c = 0; c < n; ++c) {
-        if (!solver_dims_ok(dims[c]) || !params_ok(&p[c]) || !v[c]) return GEO_EINVAL;
+        if (!solver_dims_ok(dims[c]) || !params_ok(&p[c]) || !v[c] || is_variant(&p[c])) return GEO_EINVAL;
         if (p[c].dual_storage != p[0].dual_storage) return GEO_EINVAL;
         int rc = check_ws(dims[c], &p[c], ws[c], ws_bytes[c], &L[c]);
         if (rc) return rc;
@@ -388,6 +435,10 @@ static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *w
                      int32_t n_iter, void *stream, geo_result *out, double *phase_ms,
                      int nph = GEO_NPHASE)
 {
+    if (is_variant(p)) {
+        if (!dims_ok(dims) || !params_ok(p) || !v || n_iter < 0 || phase_ms) return GEO_EINVAL;
+        return var_step_impl(dims, p, v, ws, ws_bytes, n_iter, S(stream), out);
+    }
     if (!solver_dims_ok(dims) || !params_ok(p) || !v || n_iter < 0) return GEO_EINVAL;
     Layout L;
     int rc = check_ws(dims, p, ws, ws_bytes, &L);
@@ -425,6 +476,15 @@ int geo_solve(geo_dims dims, const geo_params *p, const float *v, float *u, floa
     if (rc) return rc;
     const int step_rc = geo_step(dims, p, v, ws, ws_bytes, p->max_iter, stream, out);
     if (step_rc < 0) return step_rc;
+    if (is_variant(p)) {
+        const Dims d = to_dims(dims);
+        const hipStream_t st = S(stream);
+        rc = hip_status(var_state_io(d, p, ws, GEO_VAR_U, u, nullptr, st));
+        if (!rc) rc = hip_status(var_state_io(d, p, ws, GEO_VAR_S, s, nullptr, st));
+        if (!rc) rc = hip_status(var_state_io(d, p, ws, GEO_VAR_T, t, nullptr, st));
+        if (!rc) rc = hip_status(hipStreamSynchronize(st));
+        return rc ? rc : step_rc;
+    }
     Layout L = make_layout(dims.n1, dims.n2, dims.n3, p->dual_storage);
     const Dims d = to_dims(dims);
     const hipStream_t st = S(stream);
@@ -501,10 +561,22 @@ static int state_io(geo_dims dims, const void *ws, size_t ws_bytes, int32_t var,
     return hip_status(launch_state_io(to_dims(dims), (void *)ws, L, var, v, out, in, S(stream)));
 }
 
+static int var_state_call(geo_dims dims, const geo_params *p, const void *ws, size_t ws_bytes,
+                          int32_t var, float *out, const float *in, void *stream)
+{
+    if (!dims_ok(dims) || !params_ok(p)) return GEO_EINVAL;
+    if (var != GEO_VAR_U && var != GEO_VAR_S && var != GEO_VAR_T && var != GEO_VAR_Y1 &&
+        var != GEO_VAR_Y3 && var != GEO_VAR_Y4)
+        return GEO_EINVAL;
+    const int rc = check_var_ws(dims, p, ws, ws_bytes);
+    return rc ? rc : hip_status(var_state_io(to_dims(dims), p, (void *)ws, var, out, in, S(stream)));
+}
+
 int geo_state_get(geo_dims dims, const geo_params *p, const void *ws, size_t ws_bytes, int32_t var,
                   const float *v, float *out, void *stream)
 {
     if (!out || !p) return GEO_EINVAL;
+    if (is_variant(p)) return var_state_call(dims, p, ws, ws_bytes, var, out, nullptr, stream);
     return state_io(dims, ws, ws_bytes, var, v, out, nullptr, p->dual_storage, stream);
 }
 
@@ -512,6 +584,7 @@ int geo_state_set(geo_dims dims, const geo_params *p, void *ws, size_t ws_bytes,
                   const float *v, const float *in, void *stream)
 {
     if (!in || !p) return GEO_EINVAL;
+    if (is_variant(p)) return var_state_call(dims, p, ws, ws_bytes, var, nullptr, in, stream);
     return state_io(dims, ws, ws_bytes, var, v, nullptr, in, p->dual_storage, stream);
 }
 

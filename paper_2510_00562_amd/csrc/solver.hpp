@@ -389,6 +389,32 @@ int fallback_grid();
 hipError_t launch_fallback(const void *table, int dual_bytes, const LaunchShape &sh, int level,
                            hipStream_t st);
 
+// The comparison regularizers (variants.hip): problem (15) with SSTV or
+// HSSTV in place of GeoSSTV, plain streaming kernels around the same exact
+// l1 threshold search. Scalars kept on the device; y4 is stored as the
+// residual q = y4'/g_y - v with y4 = a4 * q (a4 = c g_y after an iteration,
+// c the fidelity-ball factor), as in the main solver.
+struct VarScalars {
+    double a4;
+    double r, rel;
+    double eps, tol;
+    uint32_t iter;       // iterations since init
+    uint32_t stop;       // stopping rule met or NaN/Inf seen: kernels are no-ops
+    uint32_t nonfinite;
+    uint32_t calls_iter; // iterations of the running call
+};
+int var_planes(int regularizer);
+size_t var_workspace_bytes(int n1, int n2, int n3, int regularizer);
+hipError_t var_state_init(const Dims &d, const geo_params *p, const float *v, void *ws,
+                          hipStream_t st);
+// n_iter iterations or fewer once the rule of eq. (28) holds; blocking;
+// fills *out and the last thresholds.
+hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws, int n_iter,
+                    hipStream_t st, VarScalars *out, double *tau_s, double *tau_t);
+// out != null: copy the variable out; otherwise load it from in.
+hipError_t var_state_io(const Dims &d, const geo_params *p, void *ws, int var, float *out,
+                        const float *in, hipStream_t st);
+
 // GEO_OK for hipSuccess, else GEO_EHIP with the error kept for
 // geo_strerror (api.hip).
 int geo_hip_status(hipError_t e);

@@ -188,3 +188,38 @@ def test_bands_beyond_the_tile_limit_are_rejected():
     assert L.geo_sweep_geometry(geo.geo_dims(4096, 4096, 1), 0, 8, 256, *[ctypes.byref(x)] * 4) == -1
     assert L.geo_workspace_size(geo.geo_dims(2048, 2048, 3), None, ctypes.byref(n)) == 0
     assert geo.geo_sweep_geometry(geo.geo_dims(2048, 2048, 3), 8)[:2] == (8, 4096)
+
+
+def test_regularizer_argument_checks_without_gpu():
+    """The comparison regularizers: the workspace size is host-side and takes
+    any dims with N < 2^31 (no tile limit); FP32 duals only; an unknown
+    regularizer, the batched and the profiled entry points give GEO_EINVAL
+    before any device work (fake non-null pointers are never dereferenced)."""
+    geo = pytest.importorskip("paper_2510_00562_amd")
+    L = geo.lib()
+    n = ctypes.c_size_t()
+    for reg in (1, 2, 3):
+        p = geo.params(1.0, 1.0, 1.0, regularizer=reg)
+        assert L.geo_workspace_size(geo.geo_dims(4096, 4096, 1), ctypes.byref(p), ctypes.byref(n)) == 0
+        N = 4096 * 4096
+        assert n.value >= (9 + (2 if reg == 1 else 4)) * 4 * N  # 9 arrays + the planes of y1
+        assert L.geo_workspace_size(geo.geo_dims(4, 5, 6), ctypes.byref(p), ctypes.byref(n)) == 0
+        small = n.value
+        assert L.geo_workspace_size(geo.geo_dims(0, 5, 6), ctypes.byref(p), ctypes.byref(n)) == -1
+        pb = geo.params(1.0, 1.0, 1.0, regularizer=reg, dual_storage=geo.GEO_STORE_BF16)
+        assert L.geo_workspace_size(geo.geo_dims(4, 5, 6), ctypes.byref(pb), ctypes.byref(n)) == -1
+        fake = ctypes.c_void_p(256)
+        d = geo.geo_dims(4, 5, 6)
+        assert L.geo_state_init(d, ctypes.byref(p), fake, fake, small - 1, None) == -2
+        ms = (ctypes.c_double * 3)()
+        assert L.geo_step_profiled(d, ctypes.byref(p), fake, fake, small, 1, None, None, ms) == -1
+        D = (geo.geo_dims * 1)(d)
+        Pa = (geo.geo_params * 1)(p)
+        V = (ctypes.c_void_p * 1)(256)
+        B = (ctypes.c_size_t * 1)(small)
+        assert L.geo_batch_step(1, D, Pa, V, V, B, fake, 1 << 20, 1, 0, None, None) == -1
+    bad = geo.params(1.0, 1.0, 1.0, regularizer=4)
+    assert L.geo_workspace_size(geo.geo_dims(4, 5, 6), ctypes.byref(bad), ctypes.byref(n)) == -1
+    assert geo.var_planes("y1", 1) == 2 and geo.var_planes("y1", 3) == 4 and geo.var_planes("y1") == 2
+    with pytest.raises(KeyError):
+        geo.var_planes("w1", 2)

@@ -1,0 +1,209 @@
+"""GPU parity of the comparison regularizers (SSTV, HSSTV1, HSSTV2 of
+Sec. IV-A, selected by geo_params.regularizer) against the FP64 oracle's
+VariantSolver: one iteration from random states (relative L2 <= 1e-6 per
+state array, r and both thresholds within 1e-6), 60 iterations from the
+initial point (u within 1e-5, the rest within 1e-4), the stopping rule of
+eq. (28) (same iteration count), the degenerate cases (zero radii, a single
+band, single rows or columns), and an identity the GPU path must keep:
+HSSTV1 with omega = 0 has the iterates of SSTV exactly (same step sizes,
+zero extra planes)."""
+import numpy as np
+import pytest
+
+from gpu_helpers import announce, dev, f32, host, rel_l2, torch_cuda
+from synth.cubes import SMALL_64x64x16, like, make_cube
+
+pytestmark = pytest.mark.gpu
+
+NAMES = {1: "sstv", 2: "hsstv1", 3: "hsstv2"}
+STATE = ("u", "s", "t", "y1", "y3", "y4")
+
+
+def planes(variant):
+    return 2 if variant == 1 else 4
+
+
+def problem(shape, seed):
+    n3, n1, n2 = shape
+    c = make_cube(like(SMALL_64x64x16, n1=n1, n2=n2, n3=n3, seed=seed, cells=5))
+    c["v"] = f32(c["v"])
+    return c
+
+
+def random_vstate(shape, variant, seed):
+    """A random state of the variant's variables: u in the box, y1 partly
+    outside the dual ball so that the conjugate prox acts."""
+    rng = np.random.default_rng(seed)
+    st = {"u": rng.uniform(0.0, 1.0, shape), "s": 0.1 * rng.standard_normal(shape),
+          "t": 0.05 * rng.standard_normal(shape),
+          "y1": rng.uniform(-1.2, 1.2, (planes(variant),) + tuple(shape)),
+          "y3": 0.1 * rng.standard_normal(shape), "y4": 0.1 * rng.standard_normal(shape)}
+    return {k: f32(v) for k, v in st.items()}
+
+
+def gpu_solver(shape, v, prm, variant):
+    import paper_2510_00562_amd as geo
+    dims = geo.dims_of(shape)
+    p = geo.params(prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"],
+                   tol=prm.get("tol", 0.0), regularizer=variant)
+    ws = geo.Workspace(geo.geo_workspace_size(dims, p))
+    vd = dev(v)
+    geo.geo_state_init(dims, p, vd, ws)
+    return geo, dims, p, ws, vd
+
+
+def get_state(geo, dims, p, ws, vd, shape, variant):
+    torch = torch_cuda()
+    out = {}
+    for name in STATE:
+        pl = geo.var_planes(name, variant)
+        t = torch.empty(((pl,) if pl > 1 else ()) + tuple(shape), dtype=torch.float32, device="cuda")
+        geo.geo_state_get(dims, p, ws, name, vd, t)
+        out[name] = t
+    torch.cuda.synchronize()
+    return {k: host(t) for k, t in out.items()}
+
+
+def radii(shape):
+    N = int(np.prod(shape))
+    # both l1 projections and the l2 ball active
+    return dict(eps=0.5 * np.sqrt(N) * 0.1, alpha=0.03 * N, beta=0.02 * N, omega=0.07)
+
+
+# (N3, N1, N2); (40, 70, 101) has more voxels than one pass of the
+# streaming kernels' grid (1024 blocks of 256 threads)
+SHAPES = [(5, 13, 70), (40, 70, 101), (1, 1, 1), (3, 1, 5), (2, 7, 1), (1, 9, 11)]
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("shape", SHAPES)
+def test_one_step_from_random_state(ora, variant, shape):
+    announce(f"{NAMES[variant]}: one step from a random state {shape}")
+    c = problem(shape, 3)
+    st = random_vstate(shape, variant, 7)
+    prm = radii(shape)
+    geo, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, variant)
+    for name in STATE:
+        geo.geo_state_set(dims, p, ws, name, vd, dev(st[name]))
+    res = geo.geo_step(dims, p, vd, ws, 1)
+    S = ora.VariantSolver(c["v"], prm["eps"], prm["alpha"], prm["beta"], variant,
+                          omega=prm["omega"], state=st)
+    S.step(1)
+    g = get_state(geo, dims, p, ws, vd, shape, variant)
+    errs = {n: rel_l2(g[n], S.state[n]) for n in STATE}
+    assert max(errs.values()) <= 1e-6, errs
+    rel, r, ts, tt = S.trace[-1]
+    assert res.iters == 1 and res.total_iters == 1
+    assert res.r == pytest.approx(r, rel=1e-6)
+    assert res.tau_s == pytest.approx(ts, rel=1e-6)
+    assert res.tau_t == pytest.approx(tt, rel=1e-6)
+    # u+ is stored in FP32: ||u+ - u|| carries up to 2^-24 ||u+|| of
+    # rounding, which dominates when u moves little (one voxel)
+    assert res.rel_change == pytest.approx(rel, rel=1e-5, abs=2.0 ** -23)
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_iterations_from_the_initial_point(ora, variant):
+    shape, n = (24, 30, 70), 60
+    announce(f"{NAMES[variant]}: {n} iterations {shape}")
+    c = problem(shape, 5)
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=0.05)
+    geo, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, variant)
+    res = geo.geo_step(dims, p, vd, ws, n)
+    assert res.iters == n and res.slots == n
+    S = ora.VariantSolver(c["v"], prm["eps"], prm["alpha"], prm["beta"], variant, omega=prm["omega"])
+    S.step(n)
+    g = get_state(geo, dims, p, ws, vd, shape, variant)
+    errs = {k: rel_l2(g[k], S.state[k]) for k in STATE if np.linalg.norm(S.state[k]) > 0}
+    print(f"{NAMES[variant]} after {n}: " + ", ".join(f"{k} {e:.1e}" for k, e in errs.items()),
+          flush=True)
+    assert errs["u"] <= 1e-5 and max(errs.values()) <= 1e-4, errs
+    rel, r, ts, tt = S.trace[-1]
+    assert res.r == pytest.approx(r, rel=1e-5)
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_stopping_rule_gives_the_oracle_count(ora, variant):
+    shape = (8, 20, 24)
+    announce(f"{NAMES[variant]}: stopping rule {shape}")
+    c = problem(shape, 9)
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=0.05, tol=2e-3)
+    geo, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, variant)
+    res = geo.geo_step(dims, p, vd, ws, 400)
+    S = ora.VariantSolver(c["v"], prm["eps"], prm["alpha"], prm["beta"], variant, omega=prm["omega"])
+    done = S.step(400, tol=prm["tol"])
+    assert done < 400 and res.converged == 1
+    assert res.iters == done, (res.iters, done, S.trace[-3:])
+    # a converged state run again stops after one more iteration
+    res2 = geo.geo_step(dims, p, vd, ws, 10)
+    assert res2.iters == 1 and res2.total_iters == done + 1
+
+
+@pytest.mark.parametrize("variant", [1, 2, 3])
+def test_zero_radii(ora, variant):
+    """alpha = beta = 0: s and t stay zero (thresholds +inf)."""
+    shape = (6, 11, 13)
+    announce(f"{NAMES[variant]}: zero radii {shape}")
+    c = problem(shape, 4)
+    prm = dict(eps=c["eps"], alpha=0.0, beta=0.0, omega=0.05)
+    geo, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, variant)
+    res = geo.geo_step(dims, p, vd, ws, 20)
+    assert res.tau_s == np.inf and res.tau_t == np.inf
+    g = get_state(geo, dims, p, ws, vd, shape, variant)
+    assert not g["s"].any() and not g["t"].any()
+    S = ora.VariantSolver(c["v"], prm["eps"], 0.0, 0.0, variant, omega=prm["omega"])
+    S.step(20)
+    assert rel_l2(g["u"], S.u) <= 1e-5
+
+
+def test_hsstv1_without_its_first_order_term_is_sstv():
+    shape = (7, 19, 23)
+    announce(f"hsstv1 omega 0 against sstv {shape}")
+    c = problem(shape, 6)
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=0.0)
+    runs = []
+    for variant in (1, 2):
+        geo, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, variant)
+        geo.geo_step(dims, p, vd, ws, 15)
+        runs.append(get_state(geo, dims, p, ws, vd, shape, variant))
+    for k in ("u", "s", "t", "y3", "y4"):
+        assert np.array_equal(runs[0][k], runs[1][k]), k
+    assert np.array_equal(runs[0]["y1"], runs[1]["y1"][:2]) and not runs[1]["y1"][2:].any()
+
+
+def test_entry_points_the_variants_do_not_take():
+    torch = torch_cuda()
+    import paper_2510_00562_amd as geo
+    shape = (4, 8, 8)
+    c = problem(shape, 1)
+    prm = radii(shape)
+    geo_, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, 1)
+    out = torch.empty(shape, dtype=torch.float32, device="cuda")
+    for name in ("w1", "w2", "y2"):
+        rc = geo.lib().geo_state_get(dims, geo.ctypes.byref(p), ws.ptr, ws.nbytes, geo.VARS[name],
+                                     None, geo.ctypes.c_void_p(out.data_ptr()), None)
+        assert rc == geo.GEO_EINVAL, name
+    with pytest.raises(geo.GeoError):
+        geo.geo_step_profiled(dims, p, vd, ws, 1)
+    table = geo.Workspace(geo.geo_batch_table_size(1))
+    with pytest.raises(geo.GeoError):
+        geo.geo_batch_step([dims], [p], [vd], [ws], table, 1)
+
+
+def test_solve_returns_the_oracle_iterates(ora):
+    torch = torch_cuda()
+    shape, n = (9, 21, 33), 40
+    announce(f"hsstv2 geo_solve {n} iterations {shape}")
+    c = problem(shape, 8)
+    import paper_2510_00562_amd as geo
+    dims = geo.dims_of(shape)
+    p = geo.params(c["eps"], c["alpha"], c["beta"], omega=0.03, max_iter=n, regularizer="hsstv2")
+    ws = geo.Workspace(geo.geo_workspace_size(dims, p))
+    vd = dev(c["v"])
+    u, s, t = (torch.empty(shape, dtype=torch.float32, device="cuda") for _ in range(3))
+    res = geo.geo_solve(dims, p, vd, u, s, t, ws)
+    assert res.iters == n and res.status == 0
+    S = ora.VariantSolver(c["v"], c["eps"], c["alpha"], c["beta"], 3, omega=0.03)
+    S.step(n)
+    assert rel_l2(host(u), S.u) <= 1e-5
+    assert rel_l2(host(s), S.s) <= 1e-4 and rel_l2(host(t), S.t) <= 1e-4
