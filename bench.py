@@ -53,14 +53,18 @@ def parse():
     ap.add_argument("--steps", type=int, default=400)
     ap.add_argument("--warmup", type=int, default=40)
     ap.add_argument("--cube", default="256x256x128", help="N1xN2xN3")
-    ap.add_argument("--workload", choices=("cube", "batch", "serve", "quality", "realshape"),
+    ap.add_argument("--workload", choices=("cube", "batch", "serve", "quality", "realshape",
+                                           "regularizer"),
                     default="cube",
                     help="cube: one cube (default); batch: 32 uneven cubes, batched launches "
                          "vs the per-cube loop; serve: a request stream through the "
                          "request loop (p50/p99 latency); quality: the paper's five noise cases "
                          "on cubes of its two image shapes, omega sweep, MPSNR/MSSIM; realshape: "
                          "the shapes and fixed radii of its real-image experiment, solved to "
-                         "tol 1e-5")
+                         "tol 1e-5; regularizer: the cube solved with a comparison "
+                         "regularizer of Sec. IV-A (--regularizer) in place of GeoSSTV")
+    ap.add_argument("--regularizer", choices=("sstv", "hsstv1", "hsstv2"), default="hsstv2",
+                    help="regularizer workload: which comparison regularizer")
     ap.add_argument("--requests", type=int, default=0,
                     help="serve: requests in the stream (0: those arriving within --seconds)")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: Poisson arrivals per second")
@@ -178,6 +182,8 @@ def main():
         return bench_quality(args)
     if args.workload == "realshape":
         return bench_realshape(args)
+    if args.workload == "regularizer":
+        return bench_regularizer(args)
     import numpy as np
     import torch
 
@@ -569,6 +575,90 @@ def bench_realshape(args):
                                "omega 0.01, solved to tol 1e-5"},
         "cubes": rows,
     }
+    print(json.dumps(out), flush=True)
+
+
+def bench_regularizer(args):
+    """The benchmark cube solved with SSTV, HSSTV1 or HSSTV2 (Sec. IV-A) in
+    place of GeoSSTV, through the same P-PDS (eq. (7)): voxel-iterations/s
+    over the timed steps and the roofline of the variant path's dominant
+    kernel, its dual kernel (HIP events around every 8th launch)."""
+    import numpy as np
+    import torch
+
+    import paper_2510_00562_amd as geo
+    from synth.cubes import CUBE_256x256x128, CUBE_512x512x224, like, make_cube
+
+    n1, n2, n3 = (int(x) for x in args.cube.lower().split("x"))
+    named = {(256, 256, 128): CUBE_256x256x128, (512, 512, 224): CUBE_512x512x224}
+    c = make_cube(named.get((n1, n2, n3)) or like(CUBE_256x256x128, n1=n1, n2=n2, n3=n3))
+    v = torch.from_numpy(np.ascontiguousarray(c["v"], dtype=np.float32)).cuda()
+    N = v.numel()
+    reg = geo.REGULARIZERS[args.regularizer]
+    P = geo.var_planes("y1", reg)
+    dims = geo.dims_of(v.shape)
+    p = geo.params(c["eps"], c["alpha"], c["beta"], omega=c["omega"], regularizer=reg)
+    ws = geo.Workspace(geo.geo_workspace_size(dims, p))
+    geo.geo_state_init(dims, p, v, ws)
+    geo.geo_step(dims, p, v, ws, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, dual_ms = geo.geo_step_timed(dims, p, v, ws, args.steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    K = args.steps
+    value = N * K / el
+    # dual kernel, per voxel: reads z_s, z_t, s, t, u+, u, the P planes of
+    # y1, y3, the y4 residual and v; writes s, t+, y3, y1 and the residual
+    dual_bytes = 4 * (13 + 2 * P)
+    # the iteration's state (u, s, t, y1, y3, y4) read and written once, v read
+    iter_bytes = 2 * 4 * (5 + P) + 4
+    avg_s = dual_ms / K / 1e3
+    achieved = dual_bytes * N / avg_s
+    out = {
+        "metric": "P-PDS voxel-iterations/s",
+        "value": value,
+        "unit": "voxel-iterations/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / K,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"P-PDS (eq. (7)) with the {args.regularizer.upper()} regularizer "
+                               f"of Sec. IV-A on one {n1}x{n2}x{n3} cube, synthetic mixed noise, "
+                               "FP32 iterates, FP64 reductions",
+                   "n1": n1, "n2": n2, "n3": n3, "voxels": N, "omega": c["omega"],
+                   "regularizer": args.regularizer},
+        "roofline": {"bound": "hbm", "kernel": "var_dual", "achieved": achieved / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK if avg_s * K <= el else None,
+                     "traffic": None, "bytes_per_voxel": dual_bytes,
+                     "avg_launch_ms": 1e3 * avg_s},
+        "iteration_bytes_per_voxel": iter_bytes,
+        "iteration_hbm_frac": iter_bytes * value / HBM_PEAK,
+        "last": {"rel_change": res.rel_change, "r": res.r, "tau_s": res.tau_s,
+                 "tau_t": res.tau_t, "iters": res.total_iters},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        vv = np.asarray(c["v"], dtype=np.float64)
+        S = oracle.VariantSolver(vv, c["eps"], c["alpha"], c["beta"], reg, omega=c["omega"])
+        S.step(1)
+        done, t1 = 0, time.perf_counter()
+        while True:
+            S.step(1)
+            done += 1
+            e2 = time.perf_counter() - t1
+            if done >= 2 and e2 >= args.cpu_seconds:
+                break
+        out["cpu_baseline"] = {"value": N * done / e2, "unit": "voxel-iterations/s",
+                               "cores": int(oracle.threads_for(N)), "kind": "oracle",
+                               "sample": f"{done} full iterations of the FP64 oracle "
+                                         f"({args.regularizer}) on the same cube ({e2:.1f} s)"}
     print(json.dumps(out), flush=True)
 
 

@@ -106,9 +106,10 @@ typedef struct {
                             <= 8 omega^2, ||D_v||^2 <= 4: u 1/33 (SSTV) or
                             1/(33 + 8 omega^2), s 1, t 1/5, duals 1/3. The
                             variants take GEO_STORE_F32 only, geo_workspace_
-                            size, geo_state_init/get/set, geo_step and
-                            geo_solve (not the batched, timed or profiled
-                            entry points: GEO_EINVAL), and any dims with
+                            size, geo_state_init/get/set, geo_step,
+                            geo_step_timed (it times the dual kernel) and
+                            geo_solve (not the batched or profiled entry
+                            points: GEO_EINVAL), and any dims with
                             N < 2^31. Their state: u, s, t, y1 (2 planes
                             [D_v D_s u, D_h D_s u] for SSTV, 4 for HSSTV
                             with [omega D_v u, omega D_h u] after them), y3
@@ -171,13 +172,15 @@ int geo_step_profiled(geo_dims dims, const geo_params *p, const float *v,
                       void *ws, size_t ws_bytes, int32_t n_iter, void *stream,
                       geo_result *out, double *phase_ms);
 
-/* geo_step with two HIP events around the fused sweep of every 8th
- * iteration slot (the first of the call included), on `stream`: the
- * kernel's launch time for a roofline. An event pair idles the GPU for a few
- * microseconds, so sampling keeps that cost out of 7 of 8 iterations.
+/* geo_step with two HIP events around the fused sweep (for the comparison
+ * regularizers: their dual kernel) of the 8th, 16th, ... iteration slot of
+ * the call (the first slot follows a host synchronisation and starts from
+ * an idle device), or of every slot in calls of fewer than 8, on `stream`:
+ * the kernel's launch time for a roofline. An event pair idles the GPU for
+ * a few microseconds, so sampling keeps that cost out of 7 of 8 iterations.
  * *sweep_a_ms (host) receives the GPU time of that kernel summed over the
  * call, estimated as the mean of the sampled launches times the number of
- * slots. */
+ * slots (iterations done, for the regularizers). */
 int geo_step_timed(geo_dims dims, const geo_params *p, const float *v,
                    void *ws, size_t ws_bytes, int32_t n_iter, void *stream,
                    geo_result *out, double *sweep_a_ms);

@@ -237,9 +237,10 @@ def geo_step_profiled(dims, p, v, ws: Workspace, n_iter: int, stream=None):
 
 
 def geo_step_timed(dims, p, v, ws: Workspace, n_iter: int, stream=None):
-    """geo_step with HIP events around the fused sweep of every 8th slot:
-    returns (geo_result, that kernel's milliseconds summed over the call,
-    estimated from the sampled launches)."""
+    """geo_step with HIP events around the fused sweep (the dual kernel for
+    the comparison regularizers) of every 8th slot: returns (geo_result, that
+    kernel's milliseconds summed over the call, estimated from the sampled
+    launches)."""
     out = geo_result()
     ms = ctypes.c_double()
     _check(lib().geo_step_timed(dims, ctypes.byref(p), _f32(v), ws.ptr, ws.nbytes, int(n_iter),

@@ -41,6 +41,7 @@ Layout make_layout(int n1, int n2, int n3, int dual_storage)
     L.winpart = take(sizeof(double) * 2 * 3 * (size_t)L.max_tiles);
     L.cand = take(sizeof(float) * 2 * (size_t)L.cap);
     L.ccount = take(sizeof(uint32_t) * 2 * (size_t)L.max_tiles);
+    L.zbuf = take(2 * f4);
     L.table = take(table_bytes(1));
     for (int p = 0; p < 2; ++p) {
         L.u[p] = take(f4);
@@ -172,13 +173,13 @@ int check_var_ws(geo_dims d, const geo_params *p, const void *ws, size_t ws_byte
 }
 
 int var_step_impl(geo_dims dims, const geo_params *p, const float *v, void *ws, size_t ws_bytes,
-                  int32_t n_iter, hipStream_t st, geo_result *out)
+                  int32_t n_iter, hipStream_t st, geo_result *out, double *dual_ms = nullptr)
 {
     int rc = check_var_ws(dims, p, ws, ws_bytes);
     if (rc) return rc;
     VarScalars x;
     double ts = 0.0, tt = 0.0;
-    rc = hip_status(var_step(to_dims(dims), p, v, ws, n_iter, st, &x, &ts, &tt));
+    rc = hip_status(var_step(to_dims(dims), p, v, ws, n_iter, st, &x, &ts, &tt, dual_ms));
     if (rc) return rc;
     const int own = x.nonfinite ? GEO_ENONFINITE : (p->tol > 0.0 && !x.stop ? GEO_MAXITER : GEO_OK);
     if (out) {
@@ -436,8 +437,10 @@ static int step_impl(geo_dims dims, const geo_params *p, const float *v, void *w
                      int nph = GEO_NPHASE)
 {
     if (is_variant(p)) {
-        if (!dims_ok(dims) || !params_ok(p) || !v || n_iter < 0 || phase_ms) return GEO_EINVAL;
-        return var_step_impl(dims, p, v, ws, ws_bytes, n_iter, S(stream), out);
+        // geo_step_timed (nph = 1) times the dual kernel; no phase profile
+        if (!dims_ok(dims) || !params_ok(p) || !v || n_iter < 0 || (phase_ms && nph != 1))
+            return GEO_EINVAL;
+        return var_step_impl(dims, p, v, ws, ws_bytes, n_iter, S(stream), out, phase_ms);
     }
     if (!solver_dims_ok(dims) || !params_ok(p) || !v || n_iter < 0) return GEO_EINVAL;
     Layout L;

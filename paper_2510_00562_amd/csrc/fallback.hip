@@ -18,7 +18,8 @@ namespace geo {
 namespace {
 
 constexpr int kFbThreads = 512;
-constexpr int kFbUnroll = 4;  // voxels per thread in flight at once
+constexpr int kFbUnroll = 4;    // voxels per thread in flight at once (from the state)
+constexpr int kFbUnrollZ = 16;  // and from stored z (one load per field and voxel)
 
 // Blocks of a pass whose voxel range [W b / G, W (b + 1) / G) meets the
 // work range [c0, c1) of a cube (empty ranges inside it count too): the
@@ -107,6 +108,9 @@ __global__ __launch_bounds__(kFbThreads) void k_fb_hist(const CubeArgs<DT> *__re
             const int par = (int)(sc->iter & 1u);
             const Side<DT> src = a.side[par];
             const float a4 = (float)sc->a4;
+            // z as sweep A stored it in this iteration, or evaluated again
+            const float *zb = sc->zstore ? a.c.zbuf : nullptr;
+            const uint32_t N = (uint32_t)d.plane;
             const uint32_t q0 = (uint32_t)((lo > c0 ? lo : c0) - c0), q1 = (uint32_t)((hi < c1 ? hi : c1) - c0);
             auto add = [&](int f, uint32_t pre, float z) {
                 const uint32_t p = abs_bits(z);
@@ -115,6 +119,26 @@ __global__ __launch_bounds__(kFbThreads) void k_fb_hist(const CubeArgs<DT> *__re
                 atomicAdd(&hc[f][b], 1u);
                 atomicAdd(&hm[f][b], (unsigned long long)significand(p));
             };
+            if (zb) {
+                for (uint32_t q = q0 + (uint32_t)tid; q < q1; q += kFbUnrollZ * kFbThreads) {
+                    float z0[kFbUnrollZ], z1[kFbUnrollZ];
+#pragma unroll
+                    for (int u = 0; u < kFbUnrollZ; ++u) {
+                        const uint32_t x = q + (uint32_t)(u * kFbThreads);
+                        z0[u] = z1[u] = 0.f;
+                        if (x < q1) {
+                            if (act0) z0[u] = zb[x];
+                            if (act1) z1[u] = zb[N + x];
+                        }
+                    }
+#pragma unroll
+                    for (int u = 0; u < kFbUnrollZ; ++u) {
+                        if (q + (uint32_t)(u * kFbThreads) >= q1) break;
+                        if (act0) add(0, pre0, z0[u]);
+                        if (act1) add(1, pre1, z1[u]);
+                    }
+                }
+            } else
             for (uint32_t q = q0 + (uint32_t)tid; q < q1; q += kFbUnroll * kFbThreads) {
                 // every load of kFbUnroll voxels first, then their bins
                 float y4s[kFbUnroll], sv[kFbUnroll], tv[kFbUnroll], y3c[kFbUnroll], y3m[kFbUnroll];

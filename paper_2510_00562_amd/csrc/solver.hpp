@@ -82,7 +82,19 @@ struct DevScalars {
     SelState sel[2];     // 0: s (alpha), 1: t (beta)
     uint32_t fallback;   // full radix searches in the current call
     uint32_t call_limit; // iterations this call may do: the cube idles after them
+    uint32_t zstore;     // sweep A of this iteration stores z_s and z_t
+    uint32_t calm;       // iterations in a row whose windows all held tau
 };
+
+// Iterations in which a threshold window is likely to miss store the inputs
+// of the two l1 projections as sweep A computes them (8 bytes per voxel), so
+// that the histogram passes of a missed window read 4 bytes per voxel and
+// field instead of evaluating them again from the state (16 bytes per
+// voxel). Likely: the first kZStoreIters iterations after the initial point
+// or a state load (tau moves fast while the duals build up), and until
+// kZStoreCalm iterations in a row have held their windows after a miss.
+constexpr uint32_t kZStoreIters = 16;
+constexpr uint32_t kZStoreCalm = 3;
 
 // A cube whose stopping rule holds, or that has done the iterations of the
 // current call, turns every kernel of a launch slot into a no-op.
@@ -93,7 +105,7 @@ __device__ __forceinline__ bool idle(const DevScalars *sc)
 
 // Offsets (bytes) of every region of a solver workspace.
 struct Layout {
-    size_t scalars, partials, hist, rec, y4p, winpart, cand, ccount, table;
+    size_t scalars, partials, hist, rec, y4p, winpart, cand, ccount, zbuf, table;
     size_t u[2], s[2], t[2], w1[2], w2[2];  // FP32 primal, ping-pong
     size_t y1[2], y2[2], y3[2], y4[2];      // duals (FP32 or BF16), ping-pong
     size_t total;
@@ -259,6 +271,7 @@ struct CubeCommon {
     FbRec *rec;         // [3 levels][2 fields] their outcomes
     float *cand;        // [2][ntiles][capt] candidate slices of the tiles
     uint32_t *ccount;   // [2][ntiles] candidates appended by each tile
+    float *zbuf;        // [2][N] z_s, z_t of an iteration that stores them
     int capt;           // candidate capacity of one tile slice
     int ntiles;
     SweepGrid g;
@@ -408,9 +421,11 @@ size_t var_workspace_bytes(int n1, int n2, int n3, int regularizer);
 hipError_t var_state_init(const Dims &d, const geo_params *p, const float *v, void *ws,
                           hipStream_t st);
 // n_iter iterations or fewer once the rule of eq. (28) holds; blocking;
-// fills *out and the last thresholds.
+// fills *out and the last thresholds. dual_ms (may be null): GPU time of
+// the dual kernel over the call, from events around a sample of launches.
 hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws, int n_iter,
-                    hipStream_t st, VarScalars *out, double *tau_s, double *tau_t);
+                    hipStream_t st, VarScalars *out, double *tau_s, double *tau_t,
+                    double *dual_ms = nullptr);
 // out != null: copy the variable out; otherwise load it from in.
 hipError_t var_state_io(const Dims &d, const geo_params *p, void *ws, int var, float *out,
                         const float *in, hipStream_t st);

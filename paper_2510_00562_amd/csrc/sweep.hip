@@ -203,6 +203,7 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
         auto vox32 = [&](int k, int i, int j) {
             return ((uint32_t)k * (uint32_t)n1 + (uint32_t)i) * (uint32_t)n2 + (uint32_t)j;
         };
+        const bool zst = sc->zstore != 0u;
         float wlo[2], whi[2];
         bool won[2];
         for (int f = 0; f < 2; ++f) {
@@ -323,6 +324,10 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
                     u2 += (double)ru_u * (double)ru_u;
                     zs = zs_of(ru_s, y4);
                     zt = zt_of(ru_t, ru_y3m, ru_y3c, y4);
+                    if (zst) {
+                        a.c.zbuf[q] = zs;
+                        a.c.zbuf[N + q] = zt;
+                    }
                 }
             }
             sU[buf][oti * WU + otj] = up;
@@ -692,9 +697,11 @@ __global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
     // a threshold found by this slot's histogram passes becomes the field's
     // search state, with the window of the next iteration sized by the
     // density of |z| around it (only this block writes the cube's state)
-    if (threadIdx.x == 0)
+    if (threadIdx.x == 0) {
+        bool missed = false;
         for (int f = 0; f < 2; ++f)
             if (!sc->sel[f].done) {
+                missed = true;
                 const FbRec &r = fb_final(cc.rec, f);
                 SelState o = sc->sel[f];
                 o.tau = r.tau;
@@ -704,6 +711,11 @@ __global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
                 set_window(o, true, window_budget(cc.d.plane));
                 sc->sel[f] = o;
             }
+        // whether the next iteration's sweep A stores z (iter counts this one)
+        const uint32_t calm = missed ? 0u : sc->calm + 1u;
+        sc->calm = calm;
+        sc->zstore = (sc->iter + 1u < kZStoreIters || calm < kZStoreCalm) ? 1u : 0u;
+    }
     // the three block sums at once, in the order of block_sum: a butterfly
     // within each wavefront, then the wavefronts in order (thread 0)
     du2 = wave_sum(du2);
@@ -774,6 +786,7 @@ __global__ __launch_bounds__(NPT) void k_init(Dims d, const float *v, Side<DT> s
         z.sel[0].radius = alpha;
         z.sel[1].radius = beta;
         z.sel[0].done = z.sel[1].done = 1u;  // no search pending
+        z.zstore = 1u;
         *sc = z;
     }
 }
@@ -870,6 +883,8 @@ __global__ void k_state_loaded(DevScalars *sc, int var)
             sc->sel[f].tau_prev2 = 0.0;
             sc->sel[f].done = 1u;
         }
+        sc->zstore = 1u;
+        sc->calm = 0u;
     }
 }
 
@@ -937,6 +952,7 @@ void cube_entry_t(CubeArgs<DT> *a, const Dims &d, const float *v, void *ws, cons
     c.hist = (Hist *)(b + L.hist);
     c.rec = (FbRec *)(b + L.rec);
     c.cand = (float *)(b + L.cand);
+    c.zbuf = (float *)(b + L.zbuf);
     c.ccount = (uint32_t *)(b + L.ccount);
     const int shape = tile_shape(d.n1, d.n2, (int)sizeof(DT));
     c.g = sweep_grid(d.n1, d.n2, d.n3, band_chunk(d.n1, d.n2, d.n3, kc, sweep_a_grid(sizeof(DT), 1 << 30), shape),

@@ -28,14 +28,20 @@
 #include <math.h>
 #include <string.h>
 
+#include <vector>
+
 #include "solver.hpp"
 
 namespace geo {
 
 namespace {
 
-constexpr int VT = 256;              // threads of the streaming kernels
-constexpr int kVarPartBlocks = 1024; // their grid (and FP64 partials per kernel)
+constexpr int VT = 256;               // threads of the streaming kernels
+// Their grid: one voxel per thread up to this many blocks (16.7M voxels),
+// grid-stride beyond; one FP64 partial per block and sum. Many short blocks
+// keep more loads in flight than a persistent grid of long loops.
+constexpr int kVarPartBlocks = 65536;
+constexpr int kFinThreads = 1024;     // the finalize's one block
 
 __device__ __forceinline__ float soft_d(float z, double tau)
 {
@@ -194,20 +200,20 @@ __global__ __launch_bounds__(VT) void k_var_dual(VarArgs a)
     if (threadIdx.x == 0) a.part[2 * kVarPartBlocks + blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(VT) void k_var_finalize(VarArgs a, int blocks)
+__global__ __launch_bounds__(kFinThreads) void k_var_finalize(VarArgs a, int blocks)
 {
-    __shared__ double red[VT / 64];
+    __shared__ double red[kFinThreads / 64];
     VarScalars *sc = a.sc;
     if (sc->stop) return;
     double du2 = 0.0, u2 = 0.0, r2 = 0.0;
-    for (int b = threadIdx.x; b < blocks; b += VT) {
+    for (int b = threadIdx.x; b < blocks; b += kFinThreads) {
         du2 += a.part[2 * b];
         u2 += a.part[2 * b + 1];
         r2 += a.part[2 * kVarPartBlocks + b];
     }
-    du2 = block_sum<VT>(du2, red);
-    u2 = block_sum<VT>(u2, red);
-    r2 = block_sum<VT>(r2, red);
+    du2 = block_sum<kFinThreads>(du2, red);
+    u2 = block_sum<kFinThreads>(u2, red);
+    r2 = block_sum<kFinThreads>(r2, red);
     if (threadIdx.x == 0) {
         const double r = sqrt(r2);
         const double rel = u2 > 0.0 ? sqrt(du2) / sqrt(u2) : __longlong_as_double(0x7ff0000000000000ll);
@@ -370,21 +376,42 @@ hipError_t var_state_init(const Dims &d, const geo_params *p, const float *v, vo
 }
 
 hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws, int n_iter,
-                    hipStream_t st, VarScalars *out, double *tau_s, double *tau_t)
+                    hipStream_t st, VarScalars *out, double *tau_s, double *tau_t, double *dual_ms)
 {
     const VarArgs a = var_args(d, p, v, ws);
     const int G = var_grid(d.plane);
-    hipLaunchKernelGGL(k_var_begin_call, dim3(1), dim3(64), 0, st, a.sc, p->eps, p->tol);
-    hipError_t e = hipGetLastError();
+    // dual_ms: events around the dual kernel of every kVarTimedEvery-th
+    // iteration from that one on (all of them in calls of fewer), the sampled
+    // times scaled to the call
+    constexpr int kVarTimedEvery = 8;
+    const bool all = n_iter < kVarTimedEvery;
+    std::vector<hipEvent_t> ev;
+    hipError_t e = hipSuccess;
+    if (dual_ms) {
+        const int ns = all ? n_iter : n_iter / kVarTimedEvery;
+        ev.resize(2 * (size_t)ns);
+        for (size_t q = 0; q < ev.size() && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
+        if (e != hipSuccess) ev.clear();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(k_var_begin_call, dim3(1), dim3(64), 0, st, a.sc, p->eps, p->tol);
+        e = hipGetLastError();
+    }
     const uint32_t *stop = &a.sc->stop;
+    size_t ne = 0;
     for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
         hipLaunchKernelGGL(k_var_primal, dim3(G), dim3(VT), 0, st, a);
         e = select_begin(a.sel, 2, p->alpha, p->beta, a.hist, stop, st);
         if (e == hipSuccess) e = select_run(a.zs, a.zt, 2, d.plane, a.sel, a.hist, stop, st);
         if (e != hipSuccess) break;
+        const bool timed = dual_ms && (all || it % kVarTimedEvery == kVarTimedEvery - 1) &&
+                           ne + 2 <= ev.size();
+        if (timed) e = hipEventRecord(ev[ne], st);
         hipLaunchKernelGGL(k_var_dual, dim3(G), dim3(VT), 0, st, a);
-        hipLaunchKernelGGL(k_var_finalize, dim3(1), dim3(VT), 0, st, a, G);
-        e = hipGetLastError();
+        if (timed && e == hipSuccess) e = hipEventRecord(ev[ne + 1], st);
+        ne += timed ? 2 : 0;
+        hipLaunchKernelGGL(k_var_finalize, dim3(1), dim3(kFinThreads), 0, st, a, G);
+        if (e == hipSuccess) e = hipGetLastError();
     }
     SelState sel[2];
     if (e == hipSuccess) e = hipMemcpyAsync(out, a.sc, sizeof(VarScalars), hipMemcpyDeviceToHost, st);
@@ -394,6 +421,19 @@ hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws
         *tau_s = sel[0].tau;
         *tau_t = sel[1].tau;
     }
+    if (e == hipSuccess && dual_ms) {
+        // iterations after the stopping rule held are no-ops: scale by the
+        // iterations done
+        double sum = 0.0;
+        for (size_t q = 0; q + 1 < ne && e == hipSuccess; q += 2) {
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
+            sum += ms;
+        }
+        const size_t ns = ne / 2;
+        *dual_ms = ns ? sum / (double)ns * (double)out->calls_iter : 0.0;
+    }
+    for (hipEvent_t x : ev) (void)hipEventDestroy(x);
     return e;
 }
 

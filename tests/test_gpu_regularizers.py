@@ -207,3 +207,25 @@ def test_solve_returns_the_oracle_iterates(ora):
     S.step(n)
     assert rel_l2(host(u), S.u) <= 1e-5
     assert rel_l2(host(s), S.s) <= 1e-4 and rel_l2(host(t), S.t) <= 1e-4
+
+
+@pytest.mark.parametrize("n", [5, 40])
+def test_timed_step_samples_the_dual_kernel(n):
+    """geo_step_timed on a variant: the same iterates as geo_step, and a dual
+    kernel time that is positive and below the call's wall time."""
+    import time
+    torch = torch_cuda()
+    shape = (32, 96, 128)
+    announce(f"sstv timed {n} iterations {shape}")
+    c = problem(shape, 2)
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=0.05)
+    geo, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res, ms = geo.geo_step_timed(dims, p, vd, ws, n)
+    wall = time.perf_counter() - t0
+    assert res.iters == n and 0.0 < ms < 1e3 * wall
+    u1 = get_state(geo, dims, p, ws, vd, shape, 1)["u"]
+    geo2, dims2, p2, ws2, vd2 = gpu_solver(shape, c["v"], prm, 1)
+    geo2.geo_step(dims2, p2, vd2, ws2, n)
+    assert np.array_equal(u1, get_state(geo2, dims2, p2, ws2, vd2, shape, 1)["u"])

@@ -52,3 +52,36 @@ def test_window_search_and_missed_windows(ora, which):
     errs = {n: rel_l2(g[n], S.state[n]) for n in STATE}
     print("rel L2:", {k: f"{e:.2e}" for k, e in errs.items()}, flush=True)
     assert errs["u"] <= 1e-5 and max(errs.values()) <= 1e-4
+
+
+def test_late_miss_evaluates_z_from_the_state(ora):
+    """A window that misses long after the start (here: after the radii of
+    (16), (17) change between calls, which moves both thresholds) is found
+    by histogram passes that evaluate z_s and z_t from the state again
+    (sweep A stores them only in the first iterations and after recent
+    misses); the thresholds and iterates must still follow the oracle."""
+    c = make_cube(batch_specs()[0])
+    v = f32(c["v"])
+    announce(f"late missed windows: batch cube 0 {v.shape}")
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=c["omega"])
+    geo, dims, p, ws, vd = gpu_solver(v.shape, v, prm)
+    res = geo.geo_step(dims, p, vd, ws, 30)
+    assert res.iters == 30
+    S = ora.Solver(v, prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"])
+    S.step(30)
+    p.alpha, p.beta = 0.5 * prm["alpha"], 0.6 * prm["beta"]
+    S.params.alpha, S.params.beta = p.alpha, p.beta
+    misses, taus = [], []
+    for _ in range(3):
+        r = geo.geo_step(dims, p, vd, ws, 1)
+        misses.append(r.fallback_passes)
+        taus.append((r.tau_s, r.tau_t))
+    S.step(3)
+    print("missed windows after the change:", misses, flush=True)
+    assert misses[0] >= 1
+    for k, (gt, ot) in enumerate(zip(taus, S.trace[30:])):
+        assert gt[0] == pytest.approx(ot[2], rel=1e-5), (k, "tau_s")
+        assert gt[1] == pytest.approx(ot[3], rel=1e-5), (k, "tau_t")
+    g = get_state(geo, dims, p, ws, vd, v.shape)
+    errs = {n: rel_l2(g[n], S.state[n]) for n in STATE}
+    assert errs["u"] <= 1e-5 and max(errs.values()) <= 1e-4, errs
