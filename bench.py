@@ -662,12 +662,17 @@ def bench_regularizer(args):
     print(json.dumps(out), flush=True)
 
 
+# the sources sweep A is compiled from (its file and the headers it includes)
+SWEEP_A_SOURCES = ("sweep.hip", "common.hpp", "radix.hpp", "solver.hpp")
+
+
 def geo_source_hash():
-    """Hash of the kernel sources (traffic counters go stale when they change)."""
+    """Hash of sweep A's sources: its traffic counters go stale when they
+    change."""
     import hashlib
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_2510_00562_amd", "csrc")
-    for f in sorted(os.listdir(d)):
+    for f in SWEEP_A_SOURCES:
         with open(os.path.join(d, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]

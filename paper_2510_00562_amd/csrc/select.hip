@@ -21,6 +21,7 @@ namespace geo {
 namespace {
 
 constexpr int kSelThreads = 256;
+constexpr int kHistUnroll = 8;  // values per thread in flight in a histogram pass
 
 
 __global__ __launch_bounds__(kSelThreads) void k_select_begin(SelState *sel, int nfields, double r0,
@@ -82,12 +83,23 @@ __global__ __launch_bounds__(kSelThreads) void k_hist(Src src, int64_t n, const 
     const uint32_t prefix = sel[f].prefix;
     const int pshift = shift + (level == 0 ? 11 : 10);
     const int64_t stride = (int64_t)gridDim.x * kSelThreads;
-    for (int64_t q = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; q < n; q += stride) {
-        uint32_t p = abs_bits(src.get(f, q));
-        if (level > 0 && (p >> pshift) != prefix) continue;
-        uint32_t b = (p >> shift) & (uint32_t)(bins - 1);
-        atomicAdd(&cnt[b], 1u);
-        atomicAdd(&ms[b], (unsigned long long)significand(p));
+    // kHistUnroll loads in flight per thread, then their bins
+    for (int64_t q0 = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; q0 < n; q0 += kHistUnroll * stride) {
+        uint32_t pv[kHistUnroll];
+#pragma unroll
+        for (int u = 0; u < kHistUnroll; ++u) {
+            const int64_t q = q0 + u * stride;
+            pv[u] = q < n ? abs_bits(src.get(f, q)) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < kHistUnroll; ++u) {
+            if (q0 + u * stride >= n) break;
+            const uint32_t p = pv[u];
+            if (level > 0 && (p >> pshift) != prefix) continue;
+            const uint32_t b = (p >> shift) & (uint32_t)(bins - 1);
+            atomicAdd(&cnt[b], 1u);
+            atomicAdd(&ms[b], (unsigned long long)significand(p));
+        }
     }
     __syncthreads();
     for (int b = threadIdx.x; b < bins; b += kSelThreads) {
@@ -98,142 +110,43 @@ __global__ __launch_bounds__(kSelThreads) void k_hist(Src src, int64_t n, const 
     }
 }
 
-// One block per field: pick the bin that holds tau, or finish.
+// One block per field: pick the bin that holds tau, or finish. The block
+// stages the level's bins in LDS and one wavefront makes the pick
+// (radix_level_wave, the same code as the solver's histogram passes).
 __global__ __launch_bounds__(kSelThreads) void k_select_level(SelState *sel, Hist *hist, int level,
                                                               const uint32_t *stop)
 {
     if (stop && *stop) return;
     const int f = blockIdx.x;
-    __shared__ SelState s;
-    __shared__ double tsum[kSelThreads];
-    __shared__ unsigned long long tcnt[kSelThreads];
-    __shared__ double sufS[kSelThreads + 1];
-    __shared__ unsigned long long sufC[kSelThreads + 1];
-    __shared__ int best;
-    if (threadIdx.x == 0) {
-        s = sel[f];
-        best = -1;
-    }
-    __syncthreads();
-    if (s.done || (int)s.level != level) return;
-    const int bins = lvl_bins(level), shift = lvl_shift(level);
-    const int per = bins / kSelThreads;  // 8 or 4
-    const int b0 = threadIdx.x * per;
-    // exponent of the values in a bin: level 0 -> from the bin index,
-    // deeper levels -> from the prefix
-    double bs[8];
-    unsigned long long bc[8];
-    double ts = 0.0;
-    unsigned long long tc = 0ull;
-    for (int q = 0; q < per; ++q) {
-        int b = b0 + q;
-        uint32_t e = level == 0 ? (uint32_t)(b >> 3) : (level == 1 ? (s.prefix >> 3) : (s.prefix >> 13));
-        double scale = ldexp(1.0, (int)(e ? e : 1u) - 150);
-        bc[q] = hist[f].count[b];
-        bs[q] = (double)hist[f].msum[b] * scale;
-    }
-    // within-thread suffix handled below; thread totals first
-    for (int q = 0; q < per; ++q) {
-        ts += bs[q];
-        tc += bc[q];
-    }
-    tsum[threadIdx.x] = ts;
-    tcnt[threadIdx.x] = tc;
-    __syncthreads();
-    if (threadIdx.x == 0) {  // fixed-order suffix over threads (deterministic)
-        double S = s.s_above;
-        unsigned long long C = s.c_above;
-        sufS[kSelThreads] = S;
-        sufC[kSelThreads] = C;
-        for (int t = kSelThreads - 1; t >= 0; --t) {
-            S += tsum[t];
-            C += tcnt[t];
-            sufS[t] = S;
-            sufC[t] = C;
-        }
-    }
-    __syncthreads();
-    const double radius = s.radius;
-    const uint32_t base = level == 0 ? 0u : (s.prefix << (level == 1 ? 20 : 10));
-    // walk this thread's bins from the top: S(b), C(b) include bin b
-    {
-        double S = sufS[threadIdx.x + 1];
-        unsigned long long C = sufC[threadIdx.x + 1];
-        int mine = -1;
-        for (int q = per - 1; q >= 0; --q) {
-            int b = b0 + q;
-            S += bs[q];
-            C += bc[q];
-            float eb = __uint_as_float(base | ((uint32_t)b << shift));
-            double fb = S - (double)eb * (double)C;
-            if (fb >= radius) {
-                mine = b;
-                break;
-            }
-        }
-        int wm = mine;  // one atomic per wavefront
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) wm = max(wm, __shfl_xor(wm, o, 64));
-        if ((threadIdx.x & 63) == 0 && wm >= 0) atomicMax(&best, wm);
-    }
-    __syncthreads();
+    __shared__ double bs[kHistBins];
+    __shared__ uint32_t bc[kHistBins];
     __shared__ uint32_t fin;
-    if (threadIdx.x == 0) {
-    int b = best;
-    // Below level 0 the lowest edge of the range has f > radius by
-    // construction; FP64 rounding of a differently ordered sum must not turn
-    // that into "inside the ball".
-    if (b < 0 && level > 0) b = 0;
-    // suffix of bins strictly above b
-    double Sab = 0.0;
-    unsigned long long Cab = 0ull;
-    {
-        int t = b < 0 ? 0 : b / per;
-        Sab = sufS[t + 1];
-        Cab = sufC[t + 1];
-        for (int bb = t * per + per - 1; bb > b; --bb) {
-            uint32_t e = level == 0 ? (uint32_t)(bb >> 3) : (level == 1 ? (s.prefix >> 3) : (s.prefix >> 13));
-            Sab += (double)hist[f].msum[bb] * ldexp(1.0, (int)(e ? e : 1u) - 150);
-            Cab += hist[f].count[bb];
-        }
+    const SelState s = sel[f];
+    if (s.done || (int)s.level != level) return;
+    const int nb = lvl_bins(level);
+    for (int b = threadIdx.x; b < nb; b += kSelThreads) {
+        bs[b] = (double)hist[f].msum[b] * bin_scale(lvl_exponent(level, s.prefix, b));
+        bc[b] = hist[f].count[b];
     }
-    SelState o = s;
-    if (b < 0) {
-        // level 0 only: f(0) = sum |z| < radius: inside the ball
-        o.tau = 0.0;
-        o.done = 1u;
-    } else {
-        uint32_t e = level == 0 ? (uint32_t)(b >> 3) : (level == 1 ? (s.prefix >> 3) : (s.prefix >> 13));
-        double bsum = (double)hist[f].msum[b] * ldexp(1.0, (int)(e ? e : 1u) - 150);
-        unsigned long long bcnt = hist[f].count[b];
-        float eb = __uint_as_float(base | ((uint32_t)b << shift));
-        double fb = (Sab + bsum) - (double)eb * (double)(Cab + bcnt);
-        if (level == 0 && b == 0 && fb <= radius) {
-            o.tau = 0.0;  // sum |z| <= radius
-            o.done = 1u;
-        } else if (fb == radius) {
-            o.tau = (double)eb;
-            o.done = 1u;
-        } else if (bcnt == 0ull || level == 2) {
-            // f linear on the bin: every value above tau lies above the bin
-            o.tau = (Sab - radius) / (double)Cab;
-            o.done = 1u;
-        } else if (bcnt == 1ull) {
-            // one value a = bsum in the bin
-            double a = bsum;
-            double t1 = Cab ? (Sab - radius) / (double)Cab : -1.0;
-            o.tau = (Cab && t1 >= a) ? t1 : (Sab + a - radius) / (double)(Cab + 1ull);
-            o.done = 1u;
-        } else {
-            o.prefix = (level == 0 ? 0u : (s.prefix << 10)) | (uint32_t)b;
-            o.c_above = Cab;
-            o.s_above = Sab;
-            o.level = (uint32_t)(level + 1);
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        RadixPick pk = {0.0, s.s_above, (double)s.c_above, 0.0, s.prefix, level, 0};
+        radix_level_wave(bs, bc, s.radius, pk);
+        if (threadIdx.x == 0) {
+            SelState o = s;
+            if (pk.done) {
+                o.tau = pk.tau;
+                o.done = 1u;
+                set_window(o, true, 0.0);
+            } else {
+                o.prefix = pk.prefix;
+                o.s_above = pk.s_above;
+                o.c_above = (uint64_t)pk.c_above;
+                o.level = (uint32_t)(level + 1);
+            }
+            sel[f] = o;
+            fin = o.done;
         }
-    }
-    if (o.done) set_window(o, true, 0.0);
-    sel[f] = o;
-    fin = o.done;
     }
     __syncthreads();
     // the next level accumulates into a clean histogram

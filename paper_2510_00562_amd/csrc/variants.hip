@@ -37,10 +37,12 @@ namespace geo {
 namespace {
 
 constexpr int VT = 256;               // threads of the streaming kernels
-// Their grid: one voxel per thread up to this many blocks (16.7M voxels),
-// grid-stride beyond; one FP64 partial per block and sum. Many short blocks
-// keep more loads in flight than a persistent grid of long loops.
-constexpr int kVarPartBlocks = 65536;
+// Their grid: one voxel per thread up to this many blocks (2M voxels),
+// grid-stride beyond; one FP64 partial per block and sum. 8192 blocks of 4
+// wavefronts fill every CU at full occupancy (32 wavefronts) several times
+// over, as many loads in flight as one voxel per thread gives, with an
+// eighth of the partials for the finalize to read.
+constexpr int kVarPartBlocks = 8192;
 constexpr int kFinThreads = 1024;     // the finalize's one block
 
 __device__ __forceinline__ float soft_d(float z, double tau)
@@ -205,11 +207,26 @@ __global__ __launch_bounds__(kFinThreads) void k_var_finalize(VarArgs a, int blo
     __shared__ double red[kFinThreads / 64];
     VarScalars *sc = a.sc;
     if (sc->stop) return;
+    // kFinUnroll partials of each sum in flight per thread (the loads of one
+    // round are independent), summed in a fixed order
+    constexpr int kFinUnroll = 8;
     double du2 = 0.0, u2 = 0.0, r2 = 0.0;
-    for (int b = threadIdx.x; b < blocks; b += kFinThreads) {
-        du2 += a.part[2 * b];
-        u2 += a.part[2 * b + 1];
-        r2 += a.part[2 * kVarPartBlocks + b];
+    for (int b0 = threadIdx.x; b0 < blocks; b0 += kFinUnroll * kFinThreads) {
+        double x0[kFinUnroll], x1[kFinUnroll], x2[kFinUnroll];
+#pragma unroll
+        for (int u = 0; u < kFinUnroll; ++u) {
+            const int b = b0 + u * kFinThreads;
+            const bool in = b < blocks;
+            x0[u] = in ? a.part[2 * b] : 0.0;
+            x1[u] = in ? a.part[2 * b + 1] : 0.0;
+            x2[u] = in ? a.part[2 * kVarPartBlocks + b] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kFinUnroll; ++u) {
+            du2 += x0[u];
+            u2 += x1[u];
+            r2 += x2[u];
+        }
     }
     du2 = block_sum<kFinThreads>(du2, red);
     u2 = block_sum<kFinThreads>(u2, red);
