@@ -17,7 +17,10 @@ namespace geo {
 
 namespace {
 
-constexpr int kFbThreads = 512;
+// One 1024-thread block per CU: the blocks' atomics on a common bin of the
+// global histogram are performed one after another, so fewer, larger blocks
+// shorten that chain.
+constexpr int kFbThreads = 1024;
 constexpr int kFbUnroll = 4;    // voxels per thread in flight at once (from the state)
 constexpr int kFbUnrollZ = 16;  // and from stored z (one load per field and voxel)
 
@@ -255,7 +258,7 @@ __global__ __launch_bounds__(kFbThreads) void k_fb_hist(const CubeArgs<DT> *__re
 
 }  // namespace
 
-// Persistent blocks of a fallback pass: two per compute unit.
+// Persistent blocks of a fallback pass: one per compute unit.
 int fallback_grid()
 {
     static const int cached = [] {
@@ -264,7 +267,7 @@ int fallback_grid()
             hipDeviceProp_t prop;
             if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
         }
-        return 2 * cus;
+        return cus;
     }();
     return cached;
 }

@@ -22,6 +22,11 @@ namespace {
 
 constexpr int kSelThreads = 256;
 constexpr int kHistUnroll = 8;  // values per thread in flight in a histogram pass
+// Histogram passes: large blocks, about one per CU and field. Every block
+// adds its LDS histogram into the field's global one with atomics, and the
+// blocks' atomics on a common bin (values cluster in a few bins) are
+// performed one after another: fewer, larger blocks shorten that chain.
+constexpr int kHistThreads = 1024;
 
 
 __global__ __launch_bounds__(kSelThreads) void k_select_begin(SelState *sel, int nfields, double r0,
@@ -65,7 +70,7 @@ struct ArraySrc {
 // Histogram of the pattern bits of one radix level, restricted to values
 // whose higher bits equal the prefix chosen by the previous levels.
 template <typename Src>
-__global__ __launch_bounds__(kSelThreads) void k_hist(Src src, int64_t n, const SelState *sel,
+__global__ __launch_bounds__(kHistThreads) void k_hist(Src src, int64_t n, const SelState *sel,
                                                       Hist *hist, int level, const uint32_t *stop)
 {
     if (stop && *stop) return;
@@ -74,7 +79,7 @@ __global__ __launch_bounds__(kSelThreads) void k_hist(Src src, int64_t n, const 
     __shared__ uint32_t cnt[kHistBins];
     __shared__ unsigned long long ms[kHistBins];
     const int bins = lvl_bins(level), shift = lvl_shift(level);
-    for (int b = threadIdx.x; b < bins; b += kSelThreads) {
+    for (int b = threadIdx.x; b < bins; b += kHistThreads) {
         cnt[b] = 0u;
         ms[b] = 0ull;
     }
@@ -82,9 +87,9 @@ __global__ __launch_bounds__(kSelThreads) void k_hist(Src src, int64_t n, const 
     src.begin();
     const uint32_t prefix = sel[f].prefix;
     const int pshift = shift + (level == 0 ? 11 : 10);
-    const int64_t stride = (int64_t)gridDim.x * kSelThreads;
+    const int64_t stride = (int64_t)gridDim.x * kHistThreads;
     // kHistUnroll loads in flight per thread, then their bins
-    for (int64_t q0 = (int64_t)blockIdx.x * kSelThreads + threadIdx.x; q0 < n; q0 += kHistUnroll * stride) {
+    for (int64_t q0 = (int64_t)blockIdx.x * kHistThreads + threadIdx.x; q0 < n; q0 += kHistUnroll * stride) {
         uint32_t pv[kHistUnroll];
 #pragma unroll
         for (int u = 0; u < kHistUnroll; ++u) {
@@ -102,7 +107,7 @@ __global__ __launch_bounds__(kSelThreads) void k_hist(Src src, int64_t n, const 
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < bins; b += kSelThreads) {
+    for (int b = threadIdx.x; b < bins; b += kHistThreads) {
         if (cnt[b]) {
             atomicAdd(&hist[f].count[b], cnt[b]);
             atomicAdd((unsigned long long *)&hist[f].msum[b], ms[b]);
@@ -728,8 +733,8 @@ int hist_blocks(int64_t n)
 {
     // 64 values per thread at most: the block histograms are flushed to
     // global memory with atomics once per block
-    int b = ceil_div(n, (int64_t)kSelThreads * 64);
-    return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+    int b = ceil_div(n, (int64_t)kHistThreads * 64);
+    return b < 1 ? 1 : (b > 256 ? 256 : b);
 }
 
 int soft_blocks(int64_t n)
@@ -757,7 +762,7 @@ hipError_t select_run(const float *z0, const float *z1, int nfields, int64_t n, 
     zp.z[1] = z1;
     const int hb = hist_blocks(n);
     for (int level = 0; level < 3; ++level) {
-        hipLaunchKernelGGL(k_hist<ArraySrc>, dim3(hb, nfields), dim3(kSelThreads), 0, st, zp, n,
+        hipLaunchKernelGGL(k_hist<ArraySrc>, dim3(hb, nfields), dim3(kHistThreads), 0, st, zp, n,
                            (const SelState *)sel, hist, level, stop);
         hipLaunchKernelGGL(k_select_level, dim3(nfields), dim3(kSelThreads), 0, st, sel, hist,
                            level, stop);
