@@ -114,9 +114,10 @@ typedef struct {
                             [D_v D_s u, D_h D_s u] for SSTV, 4 for HSSTV
                             with [omega D_v u, omega D_h u] after them), y3
                             (D_v t) and y4 (u + s + t); w1, w2 and y2 do
-                            not exist (GEO_EINVAL). The geo_result fields
-                            fallback_passes, cand_s, cand_t are 0 and slots
-                            counts iterations.                            */
+                            not exist (GEO_EINVAL). They use the same
+                            exact l1 threshold search (windows, histogram
+                            passes of a missed window in the same slot),
+                            so every geo_result field has its meaning.    */
 } geo_params;
 
 enum { GEO_REG_GEOSSTV = 0, GEO_REG_SSTV = 1, GEO_REG_HSSTV1 = 2, GEO_REG_HSSTV2 = 3 };

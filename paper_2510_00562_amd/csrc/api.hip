@@ -177,9 +177,9 @@ int var_step_impl(geo_dims dims, const geo_params *p, const float *v, void *ws, 
 {
     int rc = check_var_ws(dims, p, ws, ws_bytes);
     if (rc) return rc;
-    VarScalars x;
-    double ts = 0.0, tt = 0.0;
-    rc = hip_status(var_step(to_dims(dims), p, v, ws, n_iter, st, &x, &ts, &tt, dual_ms));
+    DevScalars x;
+    int slots = 0;
+    rc = hip_status(var_step(to_dims(dims), p, v, ws, n_iter, st, &x, &slots, dual_ms));
     if (rc) return rc;
     const int own = x.nonfinite ? GEO_ENONFINITE : (p->tol > 0.0 && !x.stop ? GEO_MAXITER : GEO_OK);
     if (out) {
@@ -188,10 +188,13 @@ int var_step_impl(geo_dims dims, const geo_params *p, const float *v, void *ws, 
         out->converged = (p->tol > 0.0 && x.stop && !x.nonfinite) ? 1 : 0;
         out->rel_change = x.rel;
         out->r = x.r;
-        out->tau_s = ts;
-        out->tau_t = tt;
+        out->tau_s = x.sel[0].tau;
+        out->tau_t = x.sel[1].tau;
         out->total_iters = (int32_t)x.iter;
-        out->slots = (int32_t)x.calls_iter;
+        out->fallback_passes = (int32_t)x.fallback;
+        out->cand_s = (int32_t)x.sel[0].cand_count;
+        out->cand_t = (int32_t)x.sel[1].cand_count;
+        out->slots = (int32_t)slots;
         out->status = own;
     }
     return own;

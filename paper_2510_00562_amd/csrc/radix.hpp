@@ -174,6 +174,25 @@ __device__ RadixPick radix_chain_block(const Hist *hist, int f, double radius, i
     return pk;
 }
 
+// Append val to this block's slice of a field's candidate list. The slot
+// comes from an LDS counter (wavefront-aggregated), so sweep A never waits on
+// a global atomic; entries past the slice's capacity are counted but
+// dropped, which the search detects as an overflow. Every lane of the
+// wavefront must call it.
+__device__ __forceinline__ void wave_append(bool want, float val, float *slice, uint32_t *lds_count,
+                                            int capb)
+{
+    const unsigned long long m = __ballot(want);
+    if (m == 0ull) return;
+    const int lane = __lane_id();
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0u;
+    if (lane == leader) base = atomicAdd(lds_count, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, 64);
+    const uint32_t off = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    if (want && base + off < (uint32_t)capb) slice[base + off] = val;
+}
+
 // Candidates a window is widened to when the density of |z| near tau is
 // known: the search handles that many in LDS at the same cost as a few.
 constexpr double kWindowFill = 16384.0;

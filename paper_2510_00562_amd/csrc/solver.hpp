@@ -84,6 +84,9 @@ struct DevScalars {
     uint32_t call_limit; // iterations this call may do: the cube idles after them
     uint32_t zstore;     // sweep A of this iteration stores z_s and z_t
     uint32_t calm;       // iterations in a row whose windows all held tau
+    uint32_t zkeep;      // z is stored in every iteration (the comparison
+                         // regularizers' path, whose primal kernel always does)
+    double gy4;          // step of y4: after an iteration y4 = gy4 c4 q
 };
 
 // Iterations in which a threshold window is likely to miss store the inputs
@@ -403,32 +406,25 @@ hipError_t launch_fallback(const void *table, int dual_bytes, const LaunchShape 
                            hipStream_t st);
 
 // The comparison regularizers (variants.hip): problem (15) with SSTV or
-// HSSTV in place of GeoSSTV, plain streaming kernels around the same exact
-// l1 threshold search. Scalars kept on the device; y4 is stored as the
-// residual q = y4'/g_y - v with y4 = a4 * q (a4 = c g_y after an iteration,
-// c the fidelity-ball factor), as in the main solver.
-struct VarScalars {
-    double a4;
-    double r, rel;
-    double eps, tol;
-    uint32_t iter;       // iterations since init
-    uint32_t stop;       // stopping rule met or NaN/Inf seen: kernels are no-ops
-    uint32_t nonfinite;
-    uint32_t calls_iter; // iterations of the running call
-};
+// HSSTV in place of GeoSSTV, with the same device scalars, window search,
+// histogram passes and finalize as the main solver.
 int var_planes(int regularizer);
 size_t var_workspace_bytes(int n1, int n2, int n3, int regularizer);
 hipError_t var_state_init(const Dims &d, const geo_params *p, const float *v, void *ws,
                           hipStream_t st);
 // n_iter iterations or fewer once the rule of eq. (28) holds; blocking;
-// fills *out and the last thresholds. dual_ms (may be null): GPU time of
-// the dual kernel over the call, from events around a sample of launches.
+// fills *out with the device scalars. dual_ms (may be null): GPU time of the
+// dual kernel over the call, from events around a sample of launches.
 hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws, int n_iter,
-                    hipStream_t st, VarScalars *out, double *tau_s, double *tau_t,
-                    double *dual_ms = nullptr);
+                    hipStream_t st, DevScalars *out, int *slots, double *dual_ms = nullptr);
 // out != null: copy the variable out; otherwise load it from in.
 hipError_t var_state_io(const Dims &d, const geo_params *p, void *ws, int var, float *out,
                         const float *in, hipStream_t st);
+
+// The finalize of a launch slot over a table of ncubes entries of `stride`
+// bytes (sweep.hip), and the scalar reset after a state load.
+hipError_t launch_finalize(const void *table, int stride, int ncubes, hipStream_t st);
+hipError_t launch_state_loaded(DevScalars *sc, int var, hipStream_t st);
 
 // GEO_OK for hipSuccess, else GEO_EHIP with the error kept for
 // geo_strerror (api.hip).

@@ -71,25 +71,6 @@ __device__ __forceinline__ float as_stored(const bf16 *, float x)
     return ld(&b);
 }
 
-// Append val to this block's slice of a field's candidate list. The slot
-// comes from an LDS counter (wavefront-aggregated), so sweep A never waits on
-// a global atomic; entries past the slice's capacity are counted but
-// dropped, which the search detects as an overflow. Every lane of the
-// wavefront must call it.
-__device__ __forceinline__ void wave_append(bool want, float val, float *slice, uint32_t *lds_count,
-                                            int capb)
-{
-    const unsigned long long m = __ballot(want);
-    if (m == 0ull) return;
-    const int lane = __lane_id();
-    const int leader = __ffsll((long long)m) - 1;
-    uint32_t base = 0u;
-    if (lane == leader) base = atomicAdd(lds_count, (uint32_t)__popcll(m));
-    base = __shfl(base, leader, 64);
-    const uint32_t off = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-    if (want && base + off < (uint32_t)capb) slice[base + off] = val;
-}
-
 // XCD-aware persistent tile order: the 8 XCDs take contiguous tile ranges so
 // that the halos shared by neighbouring tiles meet in the same L2.
 __device__ __forceinline__ int tile_at(int b, int G, int T, int r)
@@ -686,12 +667,36 @@ __global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
     __shared__ double red[3 * (NPT / 64)];
     // the partials are read together with the flag that may make them moot
     const bool skip = idle(sc);
+    // each thread adds its partials b = tid, tid + NPT, ... in that order,
+    // kFinUnroll of them loaded at a time
+    constexpr int kFinUnroll = 8;
     double du2 = 0.0, u2 = 0.0, r2 = 0.0;
-    for (int b = threadIdx.x; b < grid_a; b += NPT) {
-        du2 += part[2 * b];
-        u2 += part[2 * b + 1];
+    for (int b0 = threadIdx.x; b0 < grid_a; b0 += kFinUnroll * NPT) {
+        double x0[kFinUnroll], x1[kFinUnroll];
+#pragma unroll
+        for (int k = 0; k < kFinUnroll; ++k) {
+            const int b = b0 + k * NPT;
+            x0[k] = b < grid_a ? part[2 * b] : 0.0;
+            x1[k] = b < grid_a ? part[2 * b + 1] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kFinUnroll; ++k)
+            if (b0 + k * NPT < grid_a) {
+                du2 += x0[k];
+                u2 += x1[k];
+            }
     }
-    for (int b = threadIdx.x; b < blocks_b; b += NPT) r2 += part[2 * grid_a + b];
+    for (int b0 = threadIdx.x; b0 < blocks_b; b0 += kFinUnroll * NPT) {
+        double x2[kFinUnroll];
+#pragma unroll
+        for (int k = 0; k < kFinUnroll; ++k) {
+            const int b = b0 + k * NPT;
+            x2[k] = b < blocks_b ? part[2 * grid_a + b] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < kFinUnroll; ++k)
+            if (b0 + k * NPT < blocks_b) r2 += x2[k];
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) *slot_flags(table, (int)gridDim.x) = 0u;
     if (skip) return;
     // a threshold found by this slot's histogram passes becomes the field's
@@ -714,7 +719,7 @@ __global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
         // whether the next iteration's sweep A stores z (iter counts this one)
         const uint32_t calm = missed ? 0u : sc->calm + 1u;
         sc->calm = calm;
-        sc->zstore = (sc->iter + 1u < kZStoreIters || calm < kZStoreCalm) ? 1u : 0u;
+        sc->zstore = (sc->zkeep || sc->iter + 1u < kZStoreIters || calm < kZStoreCalm) ? 1u : 0u;
     }
     // the three block sums at once, in the order of block_sum: a butterfly
     // within each wavefront, then the wavefronts in order (thread 0)
@@ -741,7 +746,7 @@ __global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
         sc->r = r;
         sc->rel = rel;
         sc->c4 = r > sc->eps ? 1.0 - sc->eps / r : 0.0;
-        sc->a4 = 0.2 * sc->c4;
+        sc->a4 = sc->gy4 * sc->c4;
         sc->iter = sc->iter + 1u;
         sc->calls_iter = sc->calls_iter + 1u;
         if (bad) sc->nonfinite = 1u;
@@ -787,6 +792,7 @@ __global__ __launch_bounds__(NPT) void k_init(Dims d, const float *v, Side<DT> s
         z.sel[1].radius = beta;
         z.sel[0].done = z.sel[1].done = 1u;  // no search pending
         z.zstore = 1u;
+        z.gy4 = 0.2;  // the y4 step printed after eq. (24)
         *sc = z;
     }
 }
@@ -1040,6 +1046,18 @@ hipError_t launch_slot(const void *table, int dual_bytes, const LaunchShape &sh,
 {
     if (!ev) nev = 0;
     return dual_bytes == 2 ? slot_t<bf16>(table, sh, st, ev, nev) : slot_t<float>(table, sh, st, ev, nev);
+}
+
+hipError_t launch_finalize(const void *table, int stride, int ncubes, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(ncubes), dim3(NPT), 0, st, (const char *)table, stride);
+    return hipGetLastError();
+}
+
+hipError_t launch_state_loaded(DevScalars *sc, int var, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_state_loaded, dim3(1), dim3(64), 0, st, sc, var);
+    return hipGetLastError();
 }
 
 hipError_t launch_init(const Dims &d, const float *v, void *ws, const Layout &L, double eps,

@@ -8,42 +8,48 @@
 // ||D D_s||^2 <= 32, ||omega D||^2 <= 8 omega^2, ||D_v||^2 <= 4:
 //   u 1/(||A||^2 + 1), s 1, t 1/5, y 1/3.
 //
-// One iteration, on the caller's stream:
+// One launch slot per iteration, on the caller's stream, over a one-entry
+// launch table in the workspace (the layout the main solver's search,
+// histogram passes and finalize read):
 //   primal kernel: u+ = P_box(u - g_u (A^T y1 + y4)) into the other u buffer,
 //                  the inputs z_s = s - y4 and z_t = t - g_t (D_v^T y3 + y4)
-//                  of the two l1-ball projections, FP64 partials of the
-//                  stopping rule;
-//   threshold search: the exact radix search of the standalone l1
-//                  projection over z_s and z_t;
+//                  of the two l1-ball projections (stored: the histogram
+//                  passes of a missed window read them), and per block (a
+//                  "tile" of the search) the window statistics, the window
+//                  candidates and the FP64 partials of the stopping rule;
+//   window search and three histogram passes (select.hip, fallback.hip):
+//                  the exact thresholds tau_s, tau_t;
 //   dual kernel:   s+, t+ (soft thresholds), the extrapolations x' = 2 x+ - x,
 //                  y1 += g_y A u' and the conjugate prox of the regularizer
 //                  (a clip to [-1, 1], or each 4-entry group scaled into the
 //                  unit l2 ball), y3 += g_y D_v t', the y4 residual and FP64
 //                  partials of its norm;
-//   finalize:      the fidelity-ball factor (y4 - g_y P_B(y4/g_y) =
+//   finalize (sweep.hip): the fidelity-ball factor (y4 - g_y P_B(y4/g_y) =
 //                  c g_y (y4/g_y - v), c = max(0, 1 - eps/r), applied when y4
-//                  is next read), the relative change, the stopping rule.
-// A plain path on purpose: streaming kernels with grid-stride loops, the
-// stencils read through the caches, no tile fusion.
+//                  is next read), the relative change, the stopping rule, the
+//                  next windows.
+// The two streaming kernels are plain (grid-stride, the stencils read
+// through the caches); no tile fusion.
 #include <math.h>
 #include <string.h>
 
 #include <vector>
 
-#include "solver.hpp"
+#include "radix.hpp"
 
 namespace geo {
 
 namespace {
 
-constexpr int VT = 256;               // threads of the streaming kernels
-// Their grid: one voxel per thread up to this many blocks (2M voxels),
-// grid-stride beyond; one FP64 partial per block and sum. 8192 blocks of 4
-// wavefronts fill every CU at full occupancy (32 wavefronts) several times
-// over, as many loads in flight as one voxel per thread gives, with an
-// eighth of the partials for the finalize to read.
-constexpr int kVarPartBlocks = 8192;
-constexpr int kFinThreads = 1024;     // the finalize's one block
+// The primal kernel's blocks are the search's tiles: at most 1024 blocks of
+// 1024 threads (two per CU at full occupancy), so that the window search
+// scans few tile counts (with 4096 blocks of 256 threads it took 43 instead
+// of 32 us). The dual kernel runs up to 8192 blocks of 256 threads (228
+// instead of 165 us with 2048 blocks of 1024).
+constexpr int VT = 1024;          // primal, init and copy kernels
+constexpr int VTD = 256;          // dual kernel
+constexpr int kVarTiles = 1024;   // primal kernel blocks (tiles of the window search)
+constexpr int kVarBBlocks = 8192; // dual kernel blocks
 
 __device__ __forceinline__ float soft_d(float z, double tau)
 {
@@ -57,12 +63,16 @@ struct VarArgs {
     float gu, gt, gy, omega;  // step sizes, balance
     float mu_lo, mu_hi;
     const float *v;
-    VarScalars *sc;
+    DevScalars *sc;
     float *u[2], *t[2];       // ping-pong by iteration parity
-    float *s, *y1, *y3, *q, *zs, *zt;
-    double *part;             // 2 kVarPartBlocks primal partials, then kVarPartBlocks of r^2
-    SelState *sel;
-    Hist *hist;
+    float *s, *y1, *y3, *q;
+    float *z;                 // [2][N]: z_s, z_t
+    double *part;             // [2 * ntiles] primal partials, then [nb] of r^2
+    double *winpart;          // [2][ntiles][3]
+    float *cand;              // [2][ntiles][capt]
+    uint32_t *ccount;         // [2][ntiles]
+    const FbRec *rec;
+    int ntiles, nb, capt;
 };
 
 // voxel index -> (k, i, j); N < 2^31
@@ -87,46 +97,108 @@ __device__ __forceinline__ float dT(const Dims &d, const float *pv, const float 
     return a;
 }
 
+// Sums of 8 FP64 values over the block in a fixed order; valid in thread 0.
+__device__ __forceinline__ void block_sum8v(double (&x)[8], double *red /* 8 * VT/64 */)
+{
+#pragma unroll
+    for (int c = 0; c < 8; ++c) x[c] = wave_sum(x[c]);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) red[c * (VT / 64) + wid] = x[c];
+    __syncthreads();
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            double t = 0.0;
+            for (int w = 0; w < VT / 64; ++w) t += red[c * (VT / 64) + w];
+            x[c] = t;
+        }
+}
+
 __global__ __launch_bounds__(VT) void k_var_primal(VarArgs a)
 {
-    __shared__ double red[VT / 64];
-    const VarScalars *sc = a.sc;
-    if (sc->stop) return;
+    __shared__ double red[8 * (VT / 64)];
+    __shared__ uint32_t ncand[2];
+    DevScalars *sc = a.sc;
+    if (idle(sc)) return;
     const Dims d = a.d;
     const int64_t N = d.plane;
+    const int tid = threadIdx.x, b = blockIdx.x, nt = a.ntiles;
+    if (tid < 2) ncand[tid] = 0u;
     const int par = (int)(sc->iter & 1u);
     const float *u = a.u[par], *t = a.t[par];
     float *un = a.u[par ^ 1];
     const float a4 = (float)sc->a4;
     const float *y1v = a.y1, *y1h = a.y1 + N;
-    double du2 = 0.0, u2 = 0.0;
-    for (int64_t q = (int64_t)blockIdx.x * VT + threadIdx.x; q < N; q += (int64_t)gridDim.x * VT) {
-        int k, i, j;
-        coords(d, q, k, i, j);
-        // A^T y1 = D_s^T D^T (first two planes) + omega D^T (the other two)
-        float g = 0.f;
-        if (k >= 1) g += dT(d, y1v, y1h, k - 1, i, j);
-        if (k <= d.n3 - 2) g -= dT(d, y1v, y1h, k, i, j);
-        if (a.P == 4) g += a.omega * dT(d, a.y1 + 2 * N, a.y1 + 3 * N, k, i, j);
-        const float y4 = a4 * a.q[q];
-        const float uo = u[q];
-        const float x = uo - a.gu * (g + y4);
-        const float nu = fminf(fmaxf(x, a.mu_lo), a.mu_hi);
-        un[q] = nu;
-        a.zs[q] = a.s[q] - y4;
-        float dvt = 0.f;  // (D_v^T y3)(k, i, j)
-        if (i >= 1) dvt += a.y3[q - d.n2];
-        if (i <= d.n1 - 2) dvt -= a.y3[q];
-        a.zt[q] = t[q] - a.gt * (dvt + y4);
-        const double dl = (double)nu - (double)uo;
-        du2 += dl * dl;
-        u2 += (double)uo * (double)uo;
+    float wlo[2], whi[2];
+    bool won[2];
+    for (int f = 0; f < 2; ++f) {
+        won[f] = sc->sel[f].win_on != 0u;
+        wlo[f] = sc->sel[f].win_lo;
+        whi[f] = sc->sel[f].win_hi;
     }
-    const double s0 = block_sum<VT>(du2, red);
-    const double s1 = block_sum<VT>(u2, red);
-    if (threadIdx.x == 0) {
-        a.part[2 * blockIdx.x] = s0;
-        a.part[2 * blockIdx.x + 1] = s1;
+    __syncthreads();  // ncand cleared
+    double du2 = 0.0, u2 = 0.0, s_hi[2] = {0.0, 0.0}, s_all[2] = {0.0, 0.0};
+    float c_hi[2] = {0.f, 0.f};
+    // the same trip count for every lane of the block, so that whole
+    // wavefronts append candidates
+    for (int64_t q0 = (int64_t)b * VT; q0 < N; q0 += (int64_t)nt * VT) {
+        const int64_t q = q0 + tid;
+        const bool in = q < N;
+        float z[2] = {0.f, 0.f};
+        if (in) {
+            int k, i, j;
+            coords(d, q, k, i, j);
+            // A^T y1 = D_s^T D^T (first two planes) + omega D^T (the other two)
+            float g = 0.f;
+            if (k >= 1) g += dT(d, y1v, y1h, k - 1, i, j);
+            if (k <= d.n3 - 2) g -= dT(d, y1v, y1h, k, i, j);
+            if (a.P == 4) g += a.omega * dT(d, a.y1 + 2 * N, a.y1 + 3 * N, k, i, j);
+            const float y4 = a4 * a.q[q];
+            const float uo = u[q];
+            const float x = uo - a.gu * (g + y4);
+            const float nu = fminf(fmaxf(x, a.mu_lo), a.mu_hi);
+            un[q] = nu;
+            float dvt = 0.f;  // (D_v^T y3)(k, i, j)
+            if (i >= 1) dvt += a.y3[q - d.n2];
+            if (i <= d.n1 - 2) dvt -= a.y3[q];
+            z[0] = a.s[q] - y4;
+            z[1] = t[q] - a.gt * (dvt + y4);
+            a.z[q] = z[0];
+            a.z[N + q] = z[1];
+            const double dl = (double)nu - (double)uo;
+            du2 += dl * dl;
+            u2 += (double)uo * (double)uo;
+        }
+        // the window statistics and candidates of the threshold search
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            const float av = fabsf(z[f]);
+            bool cand = false;
+            if (in) {
+                s_all[f] += (double)av;
+                if (won[f]) {
+                    if (av > whi[f]) {
+                        c_hi[f] += 1.f;
+                        s_hi[f] += (double)av;
+                    } else if (av >= wlo[f]) {
+                        cand = true;
+                    }
+                }
+            }
+            wave_append(cand, av, a.cand + ((int64_t)f * nt + b) * a.capt, &ncand[f], a.capt);
+        }
+    }
+    double acc[8] = {du2, u2, (double)c_hi[0], s_hi[0], s_all[0], (double)c_hi[1], s_hi[1], s_all[1]};
+    block_sum8v(acc, red);
+    if (tid == 0) {
+        a.ccount[b] = ncand[0];
+        a.ccount[nt + b] = ncand[1];
+        a.part[2 * b] = acc[0];
+        a.part[2 * b + 1] = acc[1];
+        for (int f = 0; f < 2; ++f)
+            for (int c = 0; c < 3; ++c) a.winpart[((int64_t)f * nt + b) * 3 + c] = acc[2 + 3 * f + c];
     }
 }
 
@@ -137,31 +209,34 @@ __device__ __forceinline__ float uprime(const Dims &d, const float *un, const fl
     return 2.f * un[q] - uo[q];
 }
 
-__global__ __launch_bounds__(VT) void k_var_dual(VarArgs a)
+__global__ __launch_bounds__(VTD) void k_var_dual(VarArgs a)
 {
-    __shared__ double red[VT / 64];
-    const VarScalars *sc = a.sc;
-    if (sc->stop) return;
+    __shared__ double red[VTD / 64];
+    const DevScalars *sc = a.sc;
+    if (idle(sc)) return;
     const Dims d = a.d;
     const int64_t N = d.plane;
     const int par = (int)(sc->iter & 1u);
     const float *uo = a.u[par], *un = a.u[par ^ 1], *to = a.t[par];
     float *tn = a.t[par ^ 1];
-    const double ts = a.sel[0].tau, tt = a.sel[1].tau;
+    // the thresholds: from the window search, or from this slot's passes
+    const double ts = sc->sel[0].done ? sc->sel[0].tau : fb_final(a.rec, 0).tau;
+    const double tt = sc->sel[1].done ? sc->sel[1].tau : fb_final(a.rec, 1).tau;
     const float a4 = (float)sc->a4;
+    const float *zs = a.z, *zt = a.z + N;
     double r2 = 0.0;
-    for (int64_t q = (int64_t)blockIdx.x * VT + threadIdx.x; q < N; q += (int64_t)gridDim.x * VT) {
+    for (int64_t q = (int64_t)blockIdx.x * VTD + threadIdx.x; q < N; q += (int64_t)gridDim.x * VTD) {
         int k, i, j;
         coords(d, q, k, i, j);
-        const float so = a.s[q], sn = soft_d(a.zs[q], ts);
+        const float so = a.s[q], sn = soft_d(zs[q], ts);
         a.s[q] = sn;
         const float sp = 2.f * sn - so;
-        const float tq = soft_d(a.zt[q], tt);
+        const float tq = soft_d(zt[q], tt);
         tn[q] = tq;
         const float tp = 2.f * tq - to[q];
         // y3 += g_y D_v t' (t' one row down from its own z_t and old t)
         if (i <= d.n1 - 2) {
-            const float tp1 = 2.f * soft_d(a.zt[q + d.n2], tt) - to[q + d.n2];
+            const float tp1 = 2.f * soft_d(zt[q + d.n2], tt) - to[q + d.n2];
             a.y3[q] += a.gy * (tp1 - tp);
         }
         // A u' here: D D_s u' on the edges that exist (and omega D u')
@@ -198,55 +273,12 @@ __global__ __launch_bounds__(VT) void k_var_dual(VarArgs a)
         a.q[q] = qn;
         r2 += (double)qn * (double)qn;
     }
-    const double tot = block_sum<VT>(r2, red);
-    if (threadIdx.x == 0) a.part[2 * kVarPartBlocks + blockIdx.x] = tot;
+    const double tot = block_sum<VTD>(r2, red);
+    if (threadIdx.x == 0) a.part[2 * a.ntiles + blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(kFinThreads) void k_var_finalize(VarArgs a, int blocks)
-{
-    __shared__ double red[kFinThreads / 64];
-    VarScalars *sc = a.sc;
-    if (sc->stop) return;
-    // kFinUnroll partials of each sum in flight per thread (the loads of one
-    // round are independent), summed in a fixed order
-    constexpr int kFinUnroll = 8;
-    double du2 = 0.0, u2 = 0.0, r2 = 0.0;
-    for (int b0 = threadIdx.x; b0 < blocks; b0 += kFinUnroll * kFinThreads) {
-        double x0[kFinUnroll], x1[kFinUnroll], x2[kFinUnroll];
-#pragma unroll
-        for (int u = 0; u < kFinUnroll; ++u) {
-            const int b = b0 + u * kFinThreads;
-            const bool in = b < blocks;
-            x0[u] = in ? a.part[2 * b] : 0.0;
-            x1[u] = in ? a.part[2 * b + 1] : 0.0;
-            x2[u] = in ? a.part[2 * kVarPartBlocks + b] : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < kFinUnroll; ++u) {
-            du2 += x0[u];
-            u2 += x1[u];
-            r2 += x2[u];
-        }
-    }
-    du2 = block_sum<kFinThreads>(du2, red);
-    u2 = block_sum<kFinThreads>(u2, red);
-    r2 = block_sum<kFinThreads>(r2, red);
-    if (threadIdx.x == 0) {
-        const double r = sqrt(r2);
-        const double rel = u2 > 0.0 ? sqrt(du2) / sqrt(u2) : __longlong_as_double(0x7ff0000000000000ll);
-        const bool bad = !isfinite(du2) || !isfinite(u2) || !isfinite(r2);
-        const double c = r > sc->eps ? 1.0 - sc->eps / r : 0.0;
-        sc->r = r;
-        sc->rel = rel;
-        sc->a4 = c * (double)a.gy;
-        sc->iter = sc->iter + 1u;
-        sc->calls_iter = sc->calls_iter + 1u;
-        if (bad) sc->nonfinite = 1u;
-        if (bad || (sc->tol > 0.0 && sc->iter >= 2u && rel < sc->tol)) sc->stop = 1u;
-    }
-}
-
-__global__ __launch_bounds__(VT) void k_var_init(VarArgs a, double eps, double tol)
+__global__ __launch_bounds__(VT) void k_var_init(VarArgs a, double eps, double tol, double alpha,
+                                                 double beta, double gy4)
 {
     const int64_t N = a.d.plane;
     for (int64_t q = (int64_t)blockIdx.x * VT + threadIdx.x; q < N; q += (int64_t)gridDim.x * VT) {
@@ -258,25 +290,37 @@ __global__ __launch_bounds__(VT) void k_var_init(VarArgs a, double eps, double t
         for (int c = 0; c < a.P; ++c) a.y1[c * N + q] = 0.f;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        VarScalars z = {};
+        DevScalars z = {};
+        z.c4 = 1.0;
+        z.a4 = 1.0;
         z.eps = eps;
         z.tol = tol;
+        z.sel[0].radius = alpha;
+        z.sel[1].radius = beta;
+        z.sel[0].done = z.sel[1].done = 1u;  // no search pending
+        z.zstore = 1u;
+        z.zkeep = 1u;
+        z.gy4 = gy4;
         *a.sc = z;
     }
 }
 
-__global__ void k_var_begin_call(VarScalars *sc, double eps, double tol)
+__global__ void k_var_begin_call(DevScalars *sc, double eps, double tol, double alpha, double beta,
+                                 uint32_t limit)
 {
     if (threadIdx.x == 0) {
         sc->eps = eps;
         sc->tol = tol;
         sc->calls_iter = 0u;
+        sc->call_limit = limit;
+        sc->fallback = 0u;
+        sc->sel[0].radius = alpha;
+        sc->sel[1].radius = beta;
         sc->stop = sc->nonfinite ? 1u : 0u;
     }
 }
 
-// Copy a state variable out (out != null) or in, planes as in the C ABI. A
-// loaded y4 is kept as it is, with the factor a4 = 1.
+// Copy a state variable out (out != null) or in, planes as in the C ABI.
 __global__ __launch_bounds__(VT) void k_var_io(VarArgs a, int var, float *out, const float *in)
 {
     const int64_t N = a.d.plane;
@@ -296,38 +340,43 @@ __global__ __launch_bounds__(VT) void k_var_io(VarArgs a, int var, float *out, c
         if (out)
             out[g] = var == GEO_VAR_Y4 ? a4 * base[g] : base[g];
         else
-            base[g] = in[g];
+            base[g] = in[g];  // a loaded y4 is kept as it is, with the factor 1
     }
 }
 
-__global__ void k_var_loaded_y4(VarScalars *sc)
+int grid_of(int64_t n, int cap, int threads = VT)
 {
-    if (threadIdx.x == 0) sc->a4 = 1.0;
-}
-
-int var_grid(int64_t n)
-{
-    const int64_t b = (n + VT - 1) / VT;
-    return (int)(b < 1 ? 1 : (b > kVarPartBlocks ? kVarPartBlocks : b));
+    const int64_t b = (n + threads - 1) / threads;
+    return (int)(b < 1 ? 1 : (b > cap ? cap : b));
 }
 
 size_t align256v(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Workspace: the scalars, partials, search state, then the N-float arrays.
+// Workspace: the scalars, the search's regions, the launch table, then the
+// N-float arrays.
 struct VarLayout {
-    size_t sc, part, sel, hist, u0, u1, t0, t1, s, y1, y3, q, zs, zt, total;
+    size_t sc, part, winpart, hist, rec, cand, ccount, table, u0, u1, t0, t1, s, y1, y3, q, z, total;
+    int ntiles, nb;
+    int64_t cap;  // candidates per field
 };
 
 VarLayout var_layout(int64_t N, int P)
 {
     VarLayout L;
+    L.ntiles = grid_of(N, kVarTiles);
+    L.nb = grid_of(N, kVarBBlocks, VTD);
+    L.cap = N / 16 > 65536 ? N / 16 : 65536;
     size_t o = 0;
     auto take = [&](size_t b) { const size_t at = o; o = align256v(o + b); return at; };
     const size_t f = sizeof(float) * (size_t)N;
-    L.sc = take(sizeof(VarScalars));
-    L.part = take(sizeof(double) * 3 * kVarPartBlocks);
-    L.sel = take(2 * sizeof(SelState));
-    L.hist = take(2 * sizeof(Hist));
+    L.sc = take(sizeof(DevScalars));
+    L.part = take(sizeof(double) * (2 * (size_t)L.ntiles + (size_t)L.nb));
+    L.winpart = take(sizeof(double) * 2 * 3 * (size_t)L.ntiles);
+    L.hist = take(6 * sizeof(Hist));  // 3 radix levels x 2 fields
+    L.rec = take(6 * sizeof(FbRec));
+    L.cand = take(sizeof(float) * 2 * (size_t)L.cap);
+    L.ccount = take(sizeof(uint32_t) * 2 * (size_t)L.ntiles);
+    L.table = take(table_bytes(1));
     L.u0 = take(f);
     L.u1 = take(f);
     L.t0 = take(f);
@@ -336,13 +385,12 @@ VarLayout var_layout(int64_t N, int P)
     L.y1 = take((size_t)P * f);
     L.y3 = take(f);
     L.q = take(f);
-    L.zs = take(f);
-    L.zt = take(f);
+    L.z = take(2 * f);
     L.total = o;
     return L;
 }
 
-VarArgs var_args(const Dims &d, const geo_params *p, const float *v, void *ws)
+VarArgs var_args(const Dims &d, const geo_params *p, const float *v, void *ws, VarLayout *Lout = nullptr)
 {
     VarArgs a;
     memset(&a, 0, sizeof a);
@@ -350,6 +398,7 @@ VarArgs var_args(const Dims &d, const geo_params *p, const float *v, void *ws)
     a.variant = p->regularizer;
     a.P = var_planes(p->regularizer);
     const VarLayout L = var_layout(d.plane, a.P);
+    if (Lout) *Lout = L;
     char *b = (char *)ws;
     const double na2 = p->regularizer == GEO_REG_SSTV ? 32.0 : 32.0 + 8.0 * p->omega * p->omega;
     a.gu = (float)(1.0 / (na2 + 1.0));
@@ -359,10 +408,12 @@ VarArgs var_args(const Dims &d, const geo_params *p, const float *v, void *ws)
     a.mu_lo = (float)p->mu_lo;
     a.mu_hi = (float)p->mu_hi;
     a.v = v;
-    a.sc = (VarScalars *)(b + L.sc);
+    a.sc = (DevScalars *)(b + L.sc);
     a.part = (double *)(b + L.part);
-    a.sel = (SelState *)(b + L.sel);
-    a.hist = (Hist *)(b + L.hist);
+    a.winpart = (double *)(b + L.winpart);
+    a.cand = (float *)(b + L.cand);
+    a.ccount = (uint32_t *)(b + L.ccount);
+    a.rec = (const FbRec *)(b + L.rec);
     a.u[0] = (float *)(b + L.u0);
     a.u[1] = (float *)(b + L.u1);
     a.t[0] = (float *)(b + L.t0);
@@ -371,9 +422,38 @@ VarArgs var_args(const Dims &d, const geo_params *p, const float *v, void *ws)
     a.y1 = (float *)(b + L.y1);
     a.y3 = (float *)(b + L.y3);
     a.q = (float *)(b + L.q);
-    a.zs = (float *)(b + L.zs);
-    a.zt = (float *)(b + L.zt);
+    a.z = (float *)(b + L.z);
+    a.ntiles = L.ntiles;
+    a.nb = L.nb;
+    a.capt = (int)(L.cap / L.ntiles);
     return a;
+}
+
+// Host image of the launch table entry: the fields the window search, the
+// histogram passes and the finalize read. The tile geometry and the sweep B
+// prefetch of the main solver stay zero, and so do the state sides: the
+// passes read z from the z arrays (zkeep), never from the state.
+void var_table_entry(CubeEntry *e, const VarArgs &a, const VarLayout &L, void *ws)
+{
+    memset(e, 0, sizeof *e);
+    CubeArgs<float> *x = reinterpret_cast<CubeArgs<float> *>(e->bytes);
+    char *b = (char *)ws;
+    CubeCommon &c = x->c;
+    c.d = a.d;
+    c.v = a.v;
+    c.sc = a.sc;
+    c.part = a.part;
+    c.winpart = a.winpart;
+    c.hist = (Hist *)(b + L.hist);
+    c.rec = (FbRec *)(b + L.rec);
+    c.cand = a.cand;
+    c.ccount = a.ccount;
+    c.zbuf = a.z;
+    c.capt = a.capt;
+    c.ntiles = a.ntiles;
+    c.nb = a.nb;
+    c.mu_lo = a.mu_lo;
+    c.mu_hi = a.mu_hi;
 }
 
 }  // namespace
@@ -388,63 +468,78 @@ size_t var_workspace_bytes(int n1, int n2, int n3, int regularizer)
 hipError_t var_state_init(const Dims &d, const geo_params *p, const float *v, void *ws, hipStream_t st)
 {
     const VarArgs a = var_args(d, p, v, ws);
-    hipLaunchKernelGGL(k_var_init, dim3(var_grid(d.plane)), dim3(VT), 0, st, a, p->eps, p->tol);
+    // y4 = gy4 c4 q after an iteration, gy4 the FP32 step the kernels use
+    hipLaunchKernelGGL(k_var_init, dim3(grid_of(d.plane, kVarBBlocks)), dim3(VT), 0, st, a, p->eps,
+                       p->tol, p->alpha, p->beta, (double)a.gy);
     return hipGetLastError();
 }
 
 hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws, int n_iter,
-                    hipStream_t st, VarScalars *out, double *tau_s, double *tau_t, double *dual_ms)
+                    hipStream_t st, DevScalars *out, int *slots, double *dual_ms)
 {
-    const VarArgs a = var_args(d, p, v, ws);
-    const int G = var_grid(d.plane);
-    // dual_ms: events around the dual kernel of every kVarTimedEvery-th
-    // iteration from that one on (all of them in calls of fewer), the sampled
-    // times scaled to the call
-    constexpr int kVarTimedEvery = 8;
-    const bool all = n_iter < kVarTimedEvery;
-    std::vector<hipEvent_t> ev;
-    hipError_t e = hipSuccess;
-    if (dual_ms) {
-        const int ns = all ? n_iter : n_iter / kVarTimedEvery;
-        ev.resize(2 * (size_t)ns);
-        for (size_t q = 0; q < ev.size() && e == hipSuccess; ++q) e = hipEventCreate(&ev[q]);
-        if (e != hipSuccess) ev.clear();
-    }
+    VarLayout L;
+    const VarArgs a = var_args(d, p, v, ws, &L);
+    void *table = (char *)ws + L.table;
+    const int stride = (int)sizeof(CubeArgs<float>);
+    LaunchShape sh;
+    memset(&sh, 0, sizeof sh);
+    sh.ncubes = 1;
+    sh.fb_grid = fallback_grid();
+    // the table image, with its launch-wide flags zeroed
+    std::vector<unsigned char> img(table_bytes(1), 0);
+    var_table_entry(reinterpret_cast<CubeEntry *>(img.data()), a, L, ws);
+    hipError_t e = hipMemcpyAsync(table, img.data(), img.size(), hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(k_var_begin_call, dim3(1), dim3(64), 0, st, a.sc, p->eps, p->tol);
+        hipLaunchKernelGGL(k_var_begin_call, dim3(1), dim3(64), 0, st, a.sc, p->eps, p->tol, p->alpha,
+                           p->beta, (uint32_t)n_iter);
         e = hipGetLastError();
     }
-    const uint32_t *stop = &a.sc->stop;
+    // dual_ms: events around the dual kernel of the kTimedEvery-th,
+    // 2 kTimedEvery-th, ... slot of the call (every slot in calls of fewer),
+    // the mean scaled to the iterations done
+    const bool all = n_iter < kTimedEvery;
+    std::vector<hipEvent_t> ev;
+    if (dual_ms && e == hipSuccess) {
+        ev.resize(2 * (size_t)(all ? n_iter : n_iter / kTimedEvery));
+        for (size_t k = 0; k < ev.size() && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
+    }
+    // with a tolerance the host reads the stop flag every check_every slots
+    const int every = p->tol > 0.0 ? (p->check_every > 0 ? p->check_every : 32) : (n_iter > 0 ? n_iter : 1);
     size_t ne = 0;
-    for (int it = 0; it < n_iter && e == hipSuccess; ++it) {
-        hipLaunchKernelGGL(k_var_primal, dim3(G), dim3(VT), 0, st, a);
-        e = select_begin(a.sel, 2, p->alpha, p->beta, a.hist, stop, st);
-        if (e == hipSuccess) e = select_run(a.zs, a.zt, 2, d.plane, a.sel, a.hist, stop, st);
-        if (e != hipSuccess) break;
-        const bool timed = dual_ms && (all || it % kVarTimedEvery == kVarTimedEvery - 1) &&
-                           ne + 2 <= ev.size();
-        if (timed) e = hipEventRecord(ev[ne], st);
-        hipLaunchKernelGGL(k_var_dual, dim3(G), dim3(VT), 0, st, a);
-        if (timed && e == hipSuccess) e = hipEventRecord(ev[ne + 1], st);
-        ne += timed ? 2 : 0;
-        hipLaunchKernelGGL(k_var_finalize, dim3(1), dim3(kFinThreads), 0, st, a, G);
-        if (e == hipSuccess) e = hipGetLastError();
+    int issued = 0;
+    bool synced = false;
+    while (issued < n_iter && e == hipSuccess) {
+        const int batch = n_iter - issued < every ? n_iter - issued : every;
+        for (int it = issued; it < issued + batch && e == hipSuccess; ++it) {
+            hipLaunchKernelGGL(k_var_primal, dim3(a.ntiles), dim3(VT), 0, st, a);
+            e = launch_select_window(table, stride, 1, 0, st);
+            for (int level = 0; level < 3 && e == hipSuccess; ++level)
+                e = launch_fallback(table, 4, sh, level, st);
+            if (e != hipSuccess) break;
+            const bool timed = dual_ms && (all || it % kTimedEvery == kTimedEvery - 1) &&
+                               ne + 2 <= ev.size();
+            if (timed) e = hipEventRecord(ev[ne], st);
+            hipLaunchKernelGGL(k_var_dual, dim3(a.nb), dim3(VTD), 0, st, a);
+            if (timed && e == hipSuccess) e = hipEventRecord(ev[ne + 1], st);
+            ne += timed ? 2 : 0;
+            if (e == hipSuccess) e = launch_finalize(table, stride, 1, st);
+        }
+        issued += batch;
+        if (e == hipSuccess) e = hipMemcpyAsync(out, a.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        synced = e == hipSuccess;
+        if (synced && (out->stop || (int)out->calls_iter >= n_iter)) break;
     }
-    SelState sel[2];
-    if (e == hipSuccess) e = hipMemcpyAsync(out, a.sc, sizeof(VarScalars), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(sel, a.sel, sizeof sel, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
-    if (e == hipSuccess) {
-        *tau_s = sel[0].tau;
-        *tau_t = sel[1].tau;
+    if (!synced && e == hipSuccess) {  // n_iter = 0
+        e = hipMemcpyAsync(out, a.sc, sizeof(DevScalars), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
     }
+    *slots = issued;
     if (e == hipSuccess && dual_ms) {
-        // iterations after the stopping rule held are no-ops: scale by the
-        // iterations done
         double sum = 0.0;
-        for (size_t q = 0; q + 1 < ne && e == hipSuccess; q += 2) {
+        for (size_t k = 0; k + 1 < ne && e == hipSuccess; k += 2) {
             float ms = 0.f;
-            e = hipEventElapsedTime(&ms, ev[q], ev[q + 1]);
+            e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
             sum += ms;
         }
         const size_t ns = ne / 2;
@@ -459,9 +554,12 @@ hipError_t var_state_io(const Dims &d, const geo_params *p, void *ws, int var, f
 {
     const VarArgs a = var_args(d, p, nullptr, ws);
     const int64_t n = var == GEO_VAR_Y1 ? a.P * d.plane : d.plane;
-    hipLaunchKernelGGL(k_var_io, dim3(var_grid(n)), dim3(VT), 0, st, a, var, out, in);
-    if (in && var == GEO_VAR_Y4) hipLaunchKernelGGL(k_var_loaded_y4, dim3(1), dim3(64), 0, st, a.sc);
-    return hipGetLastError();
+    hipLaunchKernelGGL(k_var_io, dim3(grid_of(n, kVarBBlocks)), dim3(VT), 0, st, a, var, out, in);
+    hipError_t e = hipGetLastError();
+    // a loaded state does not continue the previous run: y4 read with the
+    // factor 1, the threshold predictions dropped
+    if (e == hipSuccess && in) e = launch_state_loaded(a.sc, var, st);
+    return e;
 }
 
 }  // namespace geo

@@ -111,6 +111,9 @@ def test_iterations_from_the_initial_point(ora, variant):
     geo, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, variant)
     res = geo.geo_step(dims, p, vd, ws, n)
     assert res.iters == n and res.slots == n
+    print(f"{NAMES[variant]}: missed windows {res.fallback_passes}, last window candidates "
+          f"{res.cand_s}/{res.cand_t}", flush=True)
+    assert res.fallback_passes < n // 2  # the windows hold tau most of the time
     S = ora.VariantSolver(c["v"], prm["eps"], prm["alpha"], prm["beta"], variant, omega=prm["omega"])
     S.step(n)
     g = get_state(geo, dims, p, ws, vd, shape, variant)
@@ -229,3 +232,27 @@ def test_timed_step_samples_the_dual_kernel(n):
     geo2, dims2, p2, ws2, vd2 = gpu_solver(shape, c["v"], prm, 1)
     geo2.geo_step(dims2, p2, vd2, ws2, n)
     assert np.array_equal(u1, get_state(geo2, dims2, p2, ws2, vd2, shape, 1)["u"])
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_thresholds_follow_the_oracle_every_iteration(ora, variant):
+    """One-iteration calls through the transient (windows missing, then
+    holding): every iteration's tau_s and tau_t against the oracle's."""
+    shape, n = (12, 40, 52), 24
+    announce(f"{NAMES[variant]}: thresholds per iteration {shape}")
+    c = problem(shape, 11)
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=0.05)
+    geo, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, variant)
+    taus, misses = [], []
+    for _ in range(n):
+        r = geo.geo_step(dims, p, vd, ws, 1)
+        assert r.iters == 1 and r.slots == 1
+        taus.append((r.tau_s, r.tau_t))
+        misses.append(r.fallback_passes)
+    S = ora.VariantSolver(c["v"], prm["eps"], prm["alpha"], prm["beta"], variant, omega=prm["omega"])
+    S.step(n)
+    print("missed windows:", misses, flush=True)
+    assert 0 < sum(misses) < n
+    for k, (g, o) in enumerate(zip(taus, S.trace)):
+        assert g[0] == pytest.approx(o[2], rel=1e-5, abs=1e-12), (k, "tau_s")
+        assert g[1] == pytest.approx(o[3], rel=1e-5, abs=1e-12), (k, "tau_t")
