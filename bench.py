@@ -386,7 +386,9 @@ def bench_serve(args):
     torch.cuda.synchronize()
     cap = int(args.active_mvoxels * 1e6) if args.active_mvoxels > 0 else None
     rep = run_stream(jobs, int(args.hbm_budget_gb * 2 ** 30), round_iters=25, dual_storage=store,
-                     active_voxels=cap)
+                     active_voxels=cap, keep_results=False,
+                     on_progress=lambda st: print("serve: " + ", ".join(
+                         f"{k} {v:.0f}" for k, v in st.items()), flush=True))
     done = rep.pop("jobs")
     print(f"serve: stream done in {rep['span_s']:.1f} s", flush=True)
     mean_vox = float(np.mean([j.v.size for j in done]))

@@ -122,12 +122,16 @@ class Server:
     the same throughput over more jobs and delays every one of them. None
     admits by footprint alone. overlap: copies and state set-up on a second
     stream, beside the rounds (on a host without a GPU the server keeps the
-    admission logic only)."""
+    admission logic only). keep_results: a finished job keeps its u, s, t in
+    host memory (job.u, job.s, job.t); False drops them once their copy to
+    the host has completed (a long stream's results would not fit in host
+    memory: about 3 x 45 MB for each 11M-voxel job)."""
 
     def __init__(self, hbm_budget: int, round_iters: int = 25, dual_storage: int = GEO_STORE_F32,
                  use_graph: bool = True, clock=time.perf_counter, active_voxels: int | None = None,
-                 overlap: bool = True):
+                 overlap: bool = True, keep_results: bool = True):
         self.budget = int(hbm_budget)
+        self.keep_results = keep_results
         self.active_voxels = active_voxels
         self.round_iters = int(round_iters)
         self.dual_storage = dual_storage
@@ -218,8 +222,9 @@ class Server:
                     job.finished = self.now()
                     # into pageable memory: the pinned buffers go back to the
                     # pinned-memory cache for the next jobs
-                    for name, x in host.items():
-                        setattr(job, name, x.numpy().copy())
+                    if self.keep_results:
+                        for name, x in host.items():
+                            setattr(job, name, x.numpy().copy())
                     with self._out_lock:
                         self._outbox.remove(item)
             time.sleep(0.0005)
@@ -236,7 +241,9 @@ class Server:
             dev[name] = x
         if not self.overlap:
             for name, x in dev.items():
-                setattr(job, name, x.cpu().numpy())
+                h = x.cpu().numpy()
+                if self.keep_results:
+                    setattr(job, name, h)
             job.finished = self.now()
             return [job]
         copy = self._copy_stream()
@@ -325,20 +332,28 @@ def _gpu() -> bool:
 
 def run_stream(jobs: list[Job], hbm_budget: int, round_iters: int = 25,
                dual_storage: int = GEO_STORE_F32, use_graph: bool = True,
-               active_voxels: int | None = None, overlap: bool = True) -> dict:
+               active_voxels: int | None = None, overlap: bool = True,
+               on_progress=None, progress_every_s: float = 30.0, keep_results: bool = True) -> dict:
     """Serve `jobs` (sorted by arrival, seconds from the start) in real time:
     each job is submitted when the clock reaches its arrival. Returns the
     finished jobs and the latency and throughput figures (busy_s: wall time
-    with at least one job admitted)."""
+    with at least one job admitted). on_progress (optional) is called about
+    every progress_every_s seconds with a dict of the stream's state."""
     srv = Server(hbm_budget, round_iters, dual_storage, use_graph, active_voxels=active_voxels,
-                 overlap=overlap)
+                 overlap=overlap, keep_results=keep_results)
     pending = deque(sorted(jobs, key=lambda j: j.arrival))
     busy = 0.0
+    next_report = progress_every_s
     try:
         while pending or srv.waiting or srv.active:
             now = srv.now()
             while pending and pending[0].arrival <= now:
                 srv.submit(pending.popleft())
+            if on_progress is not None and now >= next_report:
+                next_report = now + progress_every_s
+                on_progress({"t_s": now, "arrived": len(jobs) - len(pending),
+                             "waiting": len(srv.waiting), "active": len(srv.active),
+                             "finished": sum(j.finished == j.finished for j in jobs)})  # not NaN
             if not srv.waiting and not srv.active:
                 time.sleep(max(0.0, pending[0].arrival - srv.now()))
                 continue
