@@ -47,6 +47,7 @@ namespace {
 // of 32 us). The dual kernel runs up to 8192 blocks of 256 threads (228
 // instead of 165 us with 2048 blocks of 1024).
 constexpr int VT = 1024;          // primal, init and copy kernels
+constexpr int VTP4 = 512;         // primal kernel, four voxels per thread (68 VGPRs: three blocks per CU)
 constexpr int VTD = 256;          // dual kernel
 constexpr int kVarTiles = 1024;   // primal kernel blocks (tiles of the window search)
 constexpr int kVarBBlocks = 8192; // dual kernel blocks
@@ -97,21 +98,23 @@ __device__ __forceinline__ float dT(const Dims &d, const float *pv, const float 
     return a;
 }
 
-// Sums of 8 FP64 values over the block in a fixed order; valid in thread 0.
-__device__ __forceinline__ void block_sum8v(double (&x)[8], double *red /* 8 * VT/64 */)
+// Sums of 8 FP64 values over a block of NT threads in a fixed order; valid
+// in thread 0.
+template <int NT>
+__device__ __forceinline__ void block_sum8v(double (&x)[8], double *red /* 8 * NT/64 */)
 {
 #pragma unroll
     for (int c = 0; c < 8; ++c) x[c] = wave_sum(x[c]);
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     if (lane == 0)
 #pragma unroll
-        for (int c = 0; c < 8; ++c) red[c * (VT / 64) + wid] = x[c];
+        for (int c = 0; c < 8; ++c) red[c * (NT / 64) + wid] = x[c];
     __syncthreads();
     if (threadIdx.x == 0)
 #pragma unroll
         for (int c = 0; c < 8; ++c) {
             double t = 0.0;
-            for (int w = 0; w < VT / 64; ++w) t += red[c * (VT / 64) + w];
+            for (int w = 0; w < NT / 64; ++w) t += red[c * (NT / 64) + w];
             x[c] = t;
         }
 }
@@ -191,7 +194,144 @@ __global__ __launch_bounds__(VT) void k_var_primal(VarArgs a)
         }
     }
     double acc[8] = {du2, u2, (double)c_hi[0], s_hi[0], s_all[0], (double)c_hi[1], s_hi[1], s_all[1]};
-    block_sum8v(acc, red);
+    block_sum8v<VT>(acc, red);
+    if (tid == 0) {
+        a.ccount[b] = ncand[0];
+        a.ccount[nt + b] = ncand[1];
+        a.part[2 * b] = acc[0];
+        a.part[2 * b + 1] = acc[1];
+        for (int f = 0; f < 2; ++f)
+            for (int c = 0; c < 3; ++c) a.winpart[((int64_t)f * nt + b) * 3 + c] = acc[2 + 3 * f + c];
+    }
+}
+
+// ---- four voxels per thread along j (cubes with N2 % 4 == 0) ----
+// The same arithmetic as the kernels above, element by element in the same
+// order; whole 16-byte loads and stores of every array, the j - 1 and
+// j + 4 neighbours from one more scalar load.
+struct F4 {
+    float x[4];
+};
+__device__ __forceinline__ F4 ld4(const float *p)
+{
+    const float4 v = *reinterpret_cast<const float4 *>(p);
+    return F4{{v.x, v.y, v.z, v.w}};
+}
+__device__ __forceinline__ void st4(float *p, const F4 &v)
+{
+    *reinterpret_cast<float4 *>(p) = make_float4(v.x[0], v.x[1], v.x[2], v.x[3]);
+}
+
+// (D^T p)(k, i, j0 + e), e = 0..3, for the planes pv, ph
+__device__ __forceinline__ void dT4(const Dims &d, const float *pv, const float *ph, int k, int i, int j0,
+                                    float (&a)[4])
+{
+    const int64_t q = vox(d, k, i, j0);
+    F4 up = {{0.f, 0.f, 0.f, 0.f}}, cv = up;
+    if (i >= 1) up = ld4(pv + q - d.n2);
+    if (i <= d.n1 - 2) cv = ld4(pv + q);
+    const F4 h = ld4(ph + q);
+    const float hl = j0 >= 1 ? ph[q - 1] : 0.f;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int j = j0 + e;
+        float x = 0.f;
+        if (i >= 1) x += up.x[e];
+        if (i <= d.n1 - 2) x -= cv.x[e];
+        if (j >= 1) x += e ? h.x[e - 1] : hl;
+        if (j <= d.n2 - 2) x -= h.x[e];
+        a[e] = x;
+    }
+}
+
+__global__ __launch_bounds__(VTP4) void k_var_primal4(VarArgs a)
+{
+    __shared__ double red[8 * (VTP4 / 64)];
+    __shared__ uint32_t ncand[2];
+    DevScalars *sc = a.sc;
+    if (idle(sc)) return;
+    const Dims d = a.d;
+    const int64_t N = d.plane, Q = N / 4;
+    const int tid = threadIdx.x, b = blockIdx.x, nt = a.ntiles;
+    if (tid < 2) ncand[tid] = 0u;
+    const int par = (int)(sc->iter & 1u);
+    const float *u = a.u[par], *t = a.t[par];
+    float *un = a.u[par ^ 1];
+    const float a4 = (float)sc->a4;
+    const float *y1v = a.y1, *y1h = a.y1 + N;
+    float wlo[2], whi[2];
+    bool won[2];
+    for (int f = 0; f < 2; ++f) {
+        won[f] = sc->sel[f].win_on != 0u;
+        wlo[f] = sc->sel[f].win_lo;
+        whi[f] = sc->sel[f].win_hi;
+    }
+    __syncthreads();  // ncand cleared
+    double du2 = 0.0, u2 = 0.0, s_hi[2] = {0.0, 0.0}, s_all[2] = {0.0, 0.0};
+    float c_hi[2] = {0.f, 0.f};
+    for (int64_t g0 = (int64_t)b * VTP4; g0 < Q; g0 += (int64_t)nt * VTP4) {
+        const int64_t g = g0 + tid;
+        const bool in = g < Q;
+        float z[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+        if (in) {
+            const int64_t q = 4 * g;
+            int k, i, j0;
+            coords(d, q, k, i, j0);
+            float gm[4] = {0.f, 0.f, 0.f, 0.f}, gk[4] = {0.f, 0.f, 0.f, 0.f}, go[4] = {0.f, 0.f, 0.f, 0.f};
+            if (k >= 1) dT4(d, y1v, y1h, k - 1, i, j0, gm);
+            if (k <= d.n3 - 2) dT4(d, y1v, y1h, k, i, j0, gk);
+            if (a.P == 4) dT4(d, a.y1 + 2 * N, a.y1 + 3 * N, k, i, j0, go);
+            const F4 qv = ld4(a.q + q), uo = ld4(u + q), sv = ld4(a.s + q), tv = ld4(t + q);
+            F4 y3m = {{0.f, 0.f, 0.f, 0.f}}, y3c = y3m;
+            if (i >= 1) y3m = ld4(a.y3 + q - d.n2);
+            if (i <= d.n1 - 2) y3c = ld4(a.y3 + q);
+            F4 nu, zs, zt;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float gg = 0.f;
+                if (k >= 1) gg += gm[e];
+                if (k <= d.n3 - 2) gg -= gk[e];
+                if (a.P == 4) gg += a.omega * go[e];
+                const float y4 = a4 * qv.x[e];
+                const float x = uo.x[e] - a.gu * (gg + y4);
+                nu.x[e] = fminf(fmaxf(x, a.mu_lo), a.mu_hi);
+                float dvt = 0.f;
+                if (i >= 1) dvt += y3m.x[e];
+                if (i <= d.n1 - 2) dvt -= y3c.x[e];
+                zs.x[e] = sv.x[e] - y4;
+                zt.x[e] = tv.x[e] - a.gt * (dvt + y4);
+                z[0][e] = zs.x[e];
+                z[1][e] = zt.x[e];
+                const double dl = (double)nu.x[e] - (double)uo.x[e];
+                du2 += dl * dl;
+                u2 += (double)uo.x[e] * (double)uo.x[e];
+            }
+            st4(un + q, nu);
+            st4(a.z + q, zs);
+            st4(a.z + N + q, zt);
+        }
+#pragma unroll
+        for (int f = 0; f < 2; ++f)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float av = fabsf(z[f][e]);
+                bool cand = false;
+                if (in) {
+                    s_all[f] += (double)av;
+                    if (won[f]) {
+                        if (av > whi[f]) {
+                            c_hi[f] += 1.f;
+                            s_hi[f] += (double)av;
+                        } else if (av >= wlo[f]) {
+                            cand = true;
+                        }
+                    }
+                }
+                wave_append(cand, av, a.cand + ((int64_t)f * nt + b) * a.capt, &ncand[f], a.capt);
+            }
+    }
+    double acc[8] = {du2, u2, (double)c_hi[0], s_hi[0], s_all[0], (double)c_hi[1], s_hi[1], s_all[1]};
+    block_sum8v<VTP4>(acc, red);
     if (tid == 0) {
         a.ccount[b] = ncand[0];
         a.ccount[nt + b] = ncand[1];
@@ -272,6 +412,111 @@ __global__ __launch_bounds__(VTD) void k_var_dual(VarArgs a)
         const float qn = (a4 / a.gy) * a.q[q] + ((u0 + sp) + tp) - a.v[q];
         a.q[q] = qn;
         r2 += (double)qn * (double)qn;
+    }
+    const double tot = block_sum<VTD>(r2, red);
+    if (threadIdx.x == 0) a.part[2 * a.ntiles + blockIdx.x] = tot;
+}
+
+// u' = 2 u+ - u at four voxels from (k, i, j0), and at (k, i, j0 + 4)
+__device__ __forceinline__ void uprime4(const Dims &d, const float *un, const float *uo, int k, int i, int j0,
+                                        F4 &up, float &next)
+{
+    const int64_t q = vox(d, k, i, j0);
+    const F4 a = ld4(un + q), b = ld4(uo + q);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) up.x[e] = 2.f * a.x[e] - b.x[e];
+    next = j0 + 4 < d.n2 ? 2.f * un[q + 4] - uo[q + 4] : 0.f;
+}
+
+__global__ __launch_bounds__(VTD) void k_var_dual4(VarArgs a)
+{
+    __shared__ double red[VTD / 64];
+    const DevScalars *sc = a.sc;
+    if (idle(sc)) return;
+    const Dims d = a.d;
+    const int64_t N = d.plane, Q = N / 4;
+    const int par = (int)(sc->iter & 1u);
+    const float *uo = a.u[par], *un = a.u[par ^ 1], *to = a.t[par];
+    float *tn = a.t[par ^ 1];
+    const double ts = sc->sel[0].done ? sc->sel[0].tau : fb_final(a.rec, 0).tau;
+    const double tt = sc->sel[1].done ? sc->sel[1].tau : fb_final(a.rec, 1).tau;
+    const float a4 = (float)sc->a4;
+    const float *zs = a.z, *zt = a.z + N;
+    double r2 = 0.0;
+    for (int64_t g = (int64_t)blockIdx.x * VTD + threadIdx.x; g < Q; g += (int64_t)gridDim.x * VTD) {
+        const int64_t q = 4 * g;
+        int k, i, j0;
+        coords(d, q, k, i, j0);
+        const bool ei = i <= d.n1 - 2, ek = k <= d.n3 - 2;
+        const F4 zsv = ld4(zs + q), ztv = ld4(zt + q), so = ld4(a.s + q), tov = ld4(to + q);
+        F4 sn, tq, sp, tp;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            sn.x[e] = soft_d(zsv.x[e], ts);
+            sp.x[e] = 2.f * sn.x[e] - so.x[e];
+            tq.x[e] = soft_d(ztv.x[e], tt);
+            tp.x[e] = 2.f * tq.x[e] - tov.x[e];
+        }
+        st4(a.s + q, sn);
+        st4(tn + q, tq);
+        // y3 += g_y D_v t' (t' one row down from its own z_t and old t)
+        if (ei) {
+            const F4 zd = ld4(zt + q + d.n2), td = ld4(to + q + d.n2);
+            F4 y3 = ld4(a.y3 + q);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const float tp1 = 2.f * soft_d(zd.x[e], tt) - td.x[e];
+                y3.x[e] += a.gy * (tp1 - tp.x[e]);
+            }
+            st4(a.y3 + q, y3);
+        }
+        // u' on the rows (k, i), (k, i + 1), (k + 1, i), (k + 1, i + 1)
+        F4 u0, ui = {{0.f, 0.f, 0.f, 0.f}}, uk = ui, uki = ui;
+        float u0n, ukn = 0.f, dummy;
+        uprime4(d, un, uo, k, i, j0, u0, u0n);
+        if (ei) uprime4(d, un, uo, k, i + 1, j0, ui, dummy);
+        if (ek) uprime4(d, un, uo, k + 1, i, j0, uk, ukn);
+        if (ek && ei) uprime4(d, un, uo, k + 1, i + 1, j0, uki, dummy);
+        F4 yv[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < a.P) yv[c] = ld4(a.y1 + c * N + q);
+        const F4 qv = ld4(a.q + q), vv = ld4(a.v + q);
+        F4 qn;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const bool ej = j0 + e <= d.n2 - 2;
+            const float uj = ej ? (e < 3 ? u0.x[e + 1] : u0n) : 0.f;
+            float av[4] = {0.f, 0.f, 0.f, 0.f};
+            if (ek) {
+                const float s0 = uk.x[e] - u0.x[e];
+                if (ei) av[0] = (uki.x[e] - ui.x[e]) - s0;
+                if (ej) av[1] = ((e < 3 ? uk.x[e + 1] : ukn) - uj) - s0;
+            }
+            if (ei) av[2] = a.omega * (ui.x[e] - u0.x[e]);
+            if (ej) av[3] = a.omega * (uj - u0.x[e]);
+            float y[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) y[c] = c < a.P ? yv[c].x[e] + a.gy * av[c] : 0.f;
+            if (a.variant == GEO_REG_HSSTV2) {
+                const float nr = sqrtf((y[0] * y[0] + y[1] * y[1]) + (y[2] * y[2] + y[3] * y[3]));
+                if (nr > 1.f) {
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) y[c] = y[c] / nr;
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < 4; ++c) y[c] = fminf(fmaxf(y[c], -1.f), 1.f);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) yv[c].x[e] = y[c];
+            qn.x[e] = (a4 / a.gy) * qv.x[e] + ((u0.x[e] + sp.x[e]) + tp.x[e]) - vv.x[e];
+            r2 += (double)qn.x[e] * (double)qn.x[e];
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+            if (c < a.P) st4(a.y1 + c * N + q, yv[c]);
+        st4(a.q + q, qn);
     }
     const double tot = block_sum<VTD>(r2, red);
     if (threadIdx.x == 0) a.part[2 * a.ntiles + blockIdx.x] = tot;
@@ -503,6 +748,9 @@ hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws
         ev.resize(2 * (size_t)(all ? n_iter : n_iter / kTimedEvery));
         for (size_t k = 0; k < ev.size() && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
     }
+    // four voxels per thread when rows split into whole 16-byte groups and v
+    // is 16-byte aligned (the workspace arrays are 256-byte aligned)
+    const bool quads = d.n2 % 4 == 0 && ((uintptr_t)v & 15u) == 0;
     // with a tolerance the host reads the stop flag every check_every slots
     const int every = p->tol > 0.0 ? (p->check_every > 0 ? p->check_every : 32) : (n_iter > 0 ? n_iter : 1);
     size_t ne = 0;
@@ -511,7 +759,10 @@ hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws
     while (issued < n_iter && e == hipSuccess) {
         const int batch = n_iter - issued < every ? n_iter - issued : every;
         for (int it = issued; it < issued + batch && e == hipSuccess; ++it) {
-            hipLaunchKernelGGL(k_var_primal, dim3(a.ntiles), dim3(VT), 0, st, a);
+            if (quads)
+                hipLaunchKernelGGL(k_var_primal4, dim3(a.ntiles), dim3(VTP4), 0, st, a);
+            else
+                hipLaunchKernelGGL(k_var_primal, dim3(a.ntiles), dim3(VT), 0, st, a);
             e = launch_select_window(table, stride, 1, 0, st);
             for (int level = 0; level < 3 && e == hipSuccess; ++level)
                 e = launch_fallback(table, 4, sh, level, st);
@@ -519,7 +770,10 @@ hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws
             const bool timed = dual_ms && (all || it % kTimedEvery == kTimedEvery - 1) &&
                                ne + 2 <= ev.size();
             if (timed) e = hipEventRecord(ev[ne], st);
-            hipLaunchKernelGGL(k_var_dual, dim3(a.nb), dim3(VTD), 0, st, a);
+            if (quads)
+                hipLaunchKernelGGL(k_var_dual4, dim3(a.nb), dim3(VTD), 0, st, a);
+            else
+                hipLaunchKernelGGL(k_var_dual, dim3(a.nb), dim3(VTD), 0, st, a);
             if (timed && e == hipSuccess) e = hipEventRecord(ev[ne + 1], st);
             ne += timed ? 2 : 0;
             if (e == hipSuccess) e = launch_finalize(table, stride, 1, st);

@@ -71,8 +71,11 @@ def radii(shape):
 
 
 # (N3, N1, N2); (40, 70, 101) has more voxels than one pass of the
-# streaming kernels' grid (1024 blocks of 256 threads)
-SHAPES = [(5, 13, 70), (40, 70, 101), (1, 1, 1), (3, 1, 5), (2, 7, 1), (1, 9, 11)]
+# primal kernel's grid (1024 blocks of 1024 threads). Rows of a multiple of
+# 4 voxels take the four-voxels-per-thread kernels: (6, 10, 64), (3, 7, 128),
+# (1, 1, 4), (2, 5, 8), (4, 1, 12), (40, 70, 104).
+SHAPES = [(5, 13, 70), (40, 70, 101), (1, 1, 1), (3, 1, 5), (2, 7, 1), (1, 9, 11),
+          (6, 10, 64), (3, 7, 128), (1, 1, 4), (2, 5, 8), (4, 1, 12), (40, 70, 104)]
 
 
 @pytest.mark.parametrize("variant", [1, 2, 3])
@@ -103,8 +106,9 @@ def test_one_step_from_random_state(ora, variant, shape):
 
 
 @pytest.mark.parametrize("variant", [1, 2, 3])
-def test_iterations_from_the_initial_point(ora, variant):
-    shape, n = (24, 30, 70), 60
+@pytest.mark.parametrize("shape", [(24, 30, 70), (24, 30, 72)])
+def test_iterations_from_the_initial_point(ora, variant, shape):
+    n = 60
     announce(f"{NAMES[variant]}: {n} iterations {shape}")
     c = problem(shape, 5)
     prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=0.05)
@@ -159,8 +163,8 @@ def test_zero_radii(ora, variant):
     assert rel_l2(g["u"], S.u) <= 1e-5
 
 
-def test_hsstv1_without_its_first_order_term_is_sstv():
-    shape = (7, 19, 23)
+@pytest.mark.parametrize("shape", [(7, 19, 23), (7, 19, 24)])
+def test_hsstv1_without_its_first_order_term_is_sstv(shape):
     announce(f"hsstv1 omega 0 against sstv {shape}")
     c = problem(shape, 6)
     prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=0.0)
@@ -256,3 +260,32 @@ def test_thresholds_follow_the_oracle_every_iteration(ora, variant):
     for k, (g, o) in enumerate(zip(taus, S.trace)):
         assert g[0] == pytest.approx(o[2], rel=1e-5, abs=1e-12), (k, "tau_s")
         assert g[1] == pytest.approx(o[3], rel=1e-5, abs=1e-12), (k, "tau_t")
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_four_voxel_kernels_match_the_one_voxel_kernels(variant):
+    """Rows of a multiple of 4 voxels run the four-voxels-per-thread kernels
+    when v is 16-byte aligned; the same cube with v one float off alignment
+    runs the one-voxel kernels. Element by element the arithmetic is the
+    same; only the FP64 summation order of the norms differs."""
+    torch = torch_cuda()
+    import paper_2510_00562_amd as geo
+    shape, n = (9, 34, 48), 12
+    announce(f"{NAMES[variant]}: four-voxel vs one-voxel kernels {shape}")
+    c = problem(shape, 13)
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=0.05)
+    dims = geo.dims_of(shape)
+    p = geo.params(prm["eps"], prm["alpha"], prm["beta"], omega=prm["omega"], regularizer=variant)
+    N = int(np.prod(shape))
+    buf = torch.zeros(N + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = dev(c["v"]).reshape(-1)
+    states = []
+    for vd in (dev(c["v"]), buf[1:].reshape(shape)):
+        ws = geo.Workspace(geo.geo_workspace_size(dims, p))
+        geo.geo_state_init(dims, p, vd, ws)
+        geo.geo_step(dims, p, vd, ws, n)
+        states.append(get_state(geo, dims, p, ws, vd, shape, variant))
+    assert buf.data_ptr() % 16 == 0  # so buf[1:] is 4 bytes off
+    for k in STATE:
+        e = rel_l2(states[0][k], states[1][k])
+        assert e <= 1e-6, (k, e)
