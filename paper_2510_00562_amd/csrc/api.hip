@@ -303,6 +303,7 @@ static int run_cubes(int n, const geo_dims *dims, const geo_params *p, const flo
         sh.total_tiles += nt;
         sh.total_b += nb;
         sh.shape_tiles[tile_shape(dims[c].n1, dims[c].n2, L[c].dual_bytes)] += nt;
+        sh.b_kinds |= sweep_b_cpt(dims[c].n2, L[c].dual_bytes) == 4 ? 2 : 1;
     }
     sh.grid_a = sweep_a_grid(L[0].dual_bytes, sh.total_tiles);
     sh.fb_grid = fallback_grid();

@@ -335,7 +335,15 @@ struct LaunchShape {
     int shape_tiles[kTileShapes];  // sweep A tiles of the cubes of each tile shape
     int shape_grid[kTileShapes];   // persistent blocks of the sweep A launch of each shape
     int fb_grid;      // blocks of each fallback histogram pass
+    int b_kinds;      // sweep B forms present: 1 one or two columns per thread, 2 four
 };
+
+// Columns per sweep B thread for a row length: four when the row splits into
+// 16-byte groups (FP32 state), else two when it is even, else one.
+__host__ __device__ inline int sweep_b_cpt(int n2, int dual_bytes)
+{
+    return (n2 & 1) ? 1 : ((n2 & 3) == 0 && dual_bytes == 4 ? 4 : 2);
+}
 
 // Host image of one cube's table entry (FP32 or BF16 duals: same size).
 struct CubeEntry {

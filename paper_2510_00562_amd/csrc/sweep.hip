@@ -521,8 +521,58 @@ __device__ __forceinline__ void ldv_nt(const bf16 *p, float (&o)[2])
     o[0] = __uint_as_float(b << 16);
     o[1] = __uint_as_float(b & 0xffff0000u);
 }
+// four columns: one 16-byte FP32 or 8-byte BF16 access
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void ldv(const float *p, float (&o)[4])
+{
+    const float4 x = *reinterpret_cast<const float4 *>(p);
+    o[0] = x.x;
+    o[1] = x.y;
+    o[2] = x.z;
+    o[3] = x.w;
+}
+__device__ __forceinline__ void ldv(const bf16 *p, float (&o)[4])
+{
+    const uint2 b = *reinterpret_cast<const uint2 *>(p);
+    o[0] = __uint_as_float(b.x << 16);
+    o[1] = __uint_as_float(b.x & 0xffff0000u);
+    o[2] = __uint_as_float(b.y << 16);
+    o[3] = __uint_as_float(b.y & 0xffff0000u);
+}
+__device__ __forceinline__ void ldv_nt(const float *p, float (&o)[4])
+{
+    const f32x4 x = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p));
+    o[0] = x.x;
+    o[1] = x.y;
+    o[2] = x.z;
+    o[3] = x.w;
+}
+__device__ __forceinline__ void ldv_nt(const bf16 *p, float (&o)[4])
+{
+    float a[2], b[2];
+    ldv_nt(p, a);
+    ldv_nt(p + 2, b);
+    o[0] = a[0];
+    o[1] = a[1];
+    o[2] = b[0];
+    o[3] = b[1];
+}
 template <typename T>
 __device__ __forceinline__ void stv_nt(T *p, const float (&x)[1]) { st_nt(p, x[0]); }
+__device__ __forceinline__ void stv_nt(float *p, const float (&x)[4])
+{
+    f32x4 v;
+    v.x = x[0];
+    v.y = x[1];
+    v.z = x[2];
+    v.w = x[3];
+    __builtin_nontemporal_store(v, reinterpret_cast<f32x4 *>(p));
+}
+__device__ __forceinline__ void stv_nt(bf16 *p, const float (&x)[4])
+{
+    st2_nt(reinterpret_cast<bf16x2 *>(p), make_float2(x[0], x[1]));
+    st2_nt(reinterpret_cast<bf16x2 *>(p + 2), make_float2(x[2], x[3]));
+}
 __device__ __forceinline__ void stv_nt(float *p, const float (&x)[2])
 {
     st_nt(reinterpret_cast<float2 *>(p), make_float2(x[0], x[1]));
@@ -624,10 +674,10 @@ __device__ __forceinline__ double sweep_b_strips(const CubeArgs<DT> &a, const De
     return r2;
 }
 
-// Columns per sweep B thread for a row length.
-__host__ __device__ inline int sweep_b_cpt(int n2) { return (n2 & 1) ? 1 : 2; }
-
-template <typename DT>
+// WIDE: the cubes whose sweep B takes four columns per thread (a kernel of
+// their own: that form needs 104 registers, the others 73, and a kernel runs
+// at the occupancy of its largest form); otherwise the others.
+template <typename DT, bool WIDE>
 __global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh)
 {
     __shared__ double red[NPT / 64];
@@ -640,13 +690,17 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh
     __syncthreads();
     const CubeArgs<DT> &a = cubes[__builtin_amdgcn_readfirstlane(cube_of_block)];
     const DevScalars *sc = a.c.sc;
-    if (idle(sc)) return;
+    const int cpt = sweep_b_cpt(a.c.d.n2, (int)sizeof(DT));
+    if (idle(sc) || (cpt == 4) != WIDE) return;
     // a missed window's threshold comes from this slot's histogram passes
     const double ts = sc->sel[0].done ? sc->sel[0].tau : fb_final(a.c.rec, 0).tau;
     const double tt = sc->sel[1].done ? sc->sel[1].tau : fb_final(a.c.rec, 1).tau;
     const int lb = (int)blockIdx.x - a.c.b0;  // block within the cube
-    const double r2 = sweep_b_cpt(a.c.d.n2) == 2 ? sweep_b_strips<DT, 2>(a, sc, lb, ts, tt)
-                                                  : sweep_b_strips<DT, 1>(a, sc, lb, ts, tt);
+    double r2;
+    if constexpr (WIDE)
+        r2 = sweep_b_strips<DT, 4>(a, sc, lb, ts, tt);
+    else
+        r2 = cpt == 2 ? sweep_b_strips<DT, 2>(a, sc, lb, ts, tt) : sweep_b_strips<DT, 1>(a, sc, lb, ts, tt);
     const double tot = block_sum<NPT>(r2, red);
     if (threadIdx.x == 0) a.c.part[2 * a.c.ntiles + lb] = tot;
 }
@@ -969,7 +1023,7 @@ void cube_entry_t(CubeArgs<DT> *a, const Dims &d, const float *v, void *ws, cons
     {
         // strips of RB rows and CPT columns; never more blocks than the
         // partials hold
-        const int64_t items = (int64_t)d.n3 * ((d.n1 + RB - 1) / RB) * (d.n2 / sweep_b_cpt(d.n2));
+        const int64_t items = (int64_t)d.n3 * ((d.n1 + RB - 1) / RB) * (d.n2 / sweep_b_cpt(d.n2, (int)sizeof(DT)));
         const int pb = point_blocks(items);
         c.nb = pb < kSweepBBlocks ? pb : kSweepBBlocks;
     }
@@ -1013,7 +1067,11 @@ hipError_t slot_t(const void *table, const LaunchShape &sh, hipStream_t st, hipE
         e = launch_fallback(table, (int)sizeof(DT), sh, level, st);
     if (e != hipSuccess) return e;
     if (nev >= 4) (void)hipEventRecord(ev[2], st);
-    hipLaunchKernelGGL(k_sweep_b<DT>, dim3(sh.total_b), dim3(NPT), 0, st, cubes, sh);
+    if (sh.b_kinds & 1)
+        hipLaunchKernelGGL((k_sweep_b<DT, false>), dim3(sh.total_b), dim3(NPT), 0, st, cubes, sh);
+    if constexpr (sizeof(DT) == 4)  // four columns per thread with FP32 state only
+        if (sh.b_kinds & 2)
+            hipLaunchKernelGGL((k_sweep_b<DT, true>), dim3(sh.total_b), dim3(NPT), 0, st, cubes, sh);
     hipLaunchKernelGGL(k_finalize, dim3(sh.ncubes), dim3(NPT), 0, st, (const char *)table, stride);
     if (nev >= 4) (void)hipEventRecord(ev[3], st);
     return hipGetLastError();
