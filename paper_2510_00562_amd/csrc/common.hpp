@@ -84,6 +84,16 @@ __device__ __forceinline__ void st_nt(bf16 *p, float x)
     st(&b, x);
     __builtin_nontemporal_store(b.bits, &p->bits);
 }
+typedef float f32x4n __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void st_nt(float4 *p, float4 x)
+{
+    f32x4n v;
+    v.x = x.x;
+    v.y = x.y;
+    v.z = x.z;
+    v.w = x.w;
+    __builtin_nontemporal_store(v, reinterpret_cast<f32x4n *>(p));
+}
 __device__ __forceinline__ void st2_nt(float2 *p, float2 x) { st_nt(p, x); }
 __device__ __forceinline__ void st2_nt(bf16x2 *p, float2 x)
 {

@@ -253,10 +253,24 @@ template <typename DT>
 struct Side {
     using P = typename PairOf<DT>::type;
     float *u, *s, *t;
-    float2 *w1, *w2;
+    float2 *w1, *w2;  // 6 floats per voxel each: see w_udlr, w_c
     P *y1, *y2;
     DT *y3, *y4;
 };
+
+// Layout of w1 and w2 (6N floats each): the ud and lr pairs of a voxel side
+// by side, [ud_v, ud_h, lr_v, lr_h] (N float4), then the c pairs (N float2),
+// so that sweep A moves one field of a voxel in a 16-byte and an 8-byte
+// access.
+__host__ __device__ inline float4 *w_udlr(float2 *w) { return reinterpret_cast<float4 *>(w); }
+__host__ __device__ inline const float4 *w_udlr(const float2 *w) { return reinterpret_cast<const float4 *>(w); }
+__host__ __device__ inline float2 *w_c(float2 *w, int64_t n) { return w + 2 * n; }
+__host__ __device__ inline const float2 *w_c(const float2 *w, int64_t n) { return w + 2 * n; }
+// pair g (0 ud, 1 lr, 2 c) of voxel q
+__host__ __device__ inline float2 *w_pair(float2 *w, int64_t n, int g, int64_t q)
+{
+    return g < 2 ? w + 2 * q + g : w + 2 * n + q;
+}
 
 // Everything the iteration kernels need about one cube. A launch covers a
 // table of these in device memory (one entry for a single cube, up to

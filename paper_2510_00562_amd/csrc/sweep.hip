@@ -262,9 +262,17 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
                 const bool in = (o == 0 ? true : ring_w) && i >= 0 && i < n1 && j >= 0 && j < n2 && k < n3;
                 const uint32_t q = in ? vox32(k, i, j) : 0u;
 #pragma unroll
-                for (int g = 0; g < 3; ++g) {
-                    rw[o][0][g] = in ? (src.w1 + (size_t)g * N)[q] : make_float2(0.f, 0.f);
-                    rw[o][1][g] = in ? (src.w2 + (size_t)g * N)[q] : make_float2(0.f, 0.f);
+                for (int f = 0; f < 2; ++f) {
+                    const float2 *w = f ? src.w2 : src.w1;
+                    float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+                    float2 c = make_float2(0.f, 0.f);
+                    if (in) {
+                        a = w_udlr(w)[q];
+                        c = w_c(w, N)[q];
+                    }
+                    rw[o][f][0] = make_float2(a.x, a.y);
+                    rw[o][f][1] = make_float2(a.z, a.w);
+                    rw[o][f][2] = c;
                 }
             }
         };
@@ -377,8 +385,8 @@ __global__ __launch_bounds__(NT, 4) void k_sweep_a(Table<DT> cubes, LaunchShape 
                     if (o == 0) {
                         const uint32_t q = vox32(k, i, j);
                         float2 *wd = f ? dst.w2 : dst.w1;
-#pragma unroll
-                        for (int g = 0; g < 3; ++g) st_nt(wd + (size_t)g * N + q, make_float2(wn[2 * g], wn[2 * g + 1]));
+                        st_nt(w_udlr(wd) + q, make_float4(wn[0], wn[1], wn[2], wn[3]));
+                        st_nt(w_c(wd, N) + q, make_float2(wn[4], wn[5]));
                     }
 #pragma unroll
                     for (int cc = 0; cc < 6; ++cc) o6[cc] = 2.f * wn[cc] - wo[cc];
@@ -893,7 +901,7 @@ __global__ __launch_bounds__(NPT) void k_state_io(Dims d, Side<DT> s0, Side<DT> 
             case GEO_VAR_T: x = s.t[q]; break;
             case GEO_VAR_W1:
             case GEO_VAR_W2: {
-                const float2 w = wp[(pl >> 1) * N + q];
+                const float2 w = *w_pair(wp, N, pl >> 1, q);
                 x = (pl & 1) ? w.y : w.x;
             } break;
             case GEO_VAR_Y1:
@@ -912,7 +920,7 @@ __global__ __launch_bounds__(NPT) void k_state_io(Dims d, Side<DT> s0, Side<DT> 
             case GEO_VAR_T: s.t[q] = in[q]; break;
             case GEO_VAR_W1:
             case GEO_VAR_W2:
-                if ((pl & 1) == 0) wp[(pl >> 1) * N + q] = make_float2(in[g], in[g + N]);
+                if ((pl & 1) == 0) *w_pair(wp, N, pl >> 1, q) = make_float2(in[g], in[g + N]);
                 break;
             case GEO_VAR_Y1:
             case GEO_VAR_Y2:
