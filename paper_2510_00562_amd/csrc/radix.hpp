@@ -199,9 +199,11 @@ constexpr double kWindowFill = 16384.0;
 
 // Window of |z| that sweep A collects for the next iteration. tau is
 // extrapolated linearly from the last two levels, and the half-width is
-// three times the error the same extrapolation made for this iteration
-// (plus 2e-4 tau, and never less than the last step when the history is
-// short or the prediction failed). budget > 0 and the density of |z| near
+// twice the error the same extrapolation made for this iteration (plus
+// 5e-5 tau, and never less than the last step plus 2e-4 tau when the
+// history is short or the prediction failed). Three times the error plus
+// 2e-4 tau held as well in steady state, with windows a third wider: the
+// 512 x 512 x 224 search took 89 instead of 51 us. budget > 0 and the density of |z| near
 // tau known from this iteration: the window is widened to hold about
 // kWindowFill values (the search's cost is flat up to there, and a wider
 // window misses less) and narrowed to hold at most about `budget` (a window
@@ -220,7 +222,7 @@ __device__ inline void set_window(SelState &o, bool missed, double budget)
     const bool h1 = t1 > 0.0 && isfinite(t1), h2 = h1 && t2 > 0.0 && isfinite(t2);
     const double step = h1 ? tau - t1 : 0.05 * tau;
     const double err = h2 ? fabs(tau - (2.0 * t1 - t2)) : fabs(step);
-    double h = 3.0 * err + 2e-4 * tau;
+    double h = 2.0 * err + 5e-5 * tau;
     if (!h2 || missed) h = fmax(h, fabs(step) + 2e-4 * tau);
     const double c = tau + (h1 ? step : 0.0);
     if (budget > 0.0 && o.dens > 0.0) {
