@@ -693,7 +693,8 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
             // density of |z| in this iteration's window, for the next one's size
             const double wdt = (double)s.win_hi - (double)s.win_lo;
             o.dens = (s.win_on && wdt > 0.0) ? (double)o.cand_count / wdt : 0.0;
-            set_window(o, false, window_budget(cc.d.plane));
+            set_window(o, false, window_budget(cc.d.plane),
+                       sc->calm >= kCalmNarrow ? kWindowFillCalm : kWindowFill);
         } else {
             // the radix levels over the whole field, by the histogram passes
             // that follow in this launch slot (fallback.hip)
