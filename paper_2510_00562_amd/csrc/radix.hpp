@@ -197,10 +197,11 @@ __device__ __forceinline__ void wave_append(bool want, float val, float *slice, 
 // known: the search handles that many in LDS at almost the same cost as a
 // few, and a wider window misses less. Once the windows have held for
 // kCalmNarrow iterations in a row (tau moves smoothly) the narrower fill
-// saves sweep A's appends and the search's bins (256 x 256 x 128: 0.362 to
-// 0.357 ms per iteration); from the start it would miss more.
+// saves sweep A's appends and the search's bins (256 x 256 x 128: 0.362 ms
+// per iteration at 16384 candidates, 0.357 at 8192, 0.3555 at 4096); from
+// the start it would miss more.
 constexpr double kWindowFill = 16384.0;
-constexpr double kWindowFillCalm = 8192.0;
+constexpr double kWindowFillCalm = 4096.0;
 constexpr uint32_t kCalmNarrow = 8;
 
 // Window of |z| that sweep A collects for the next iteration. tau is
