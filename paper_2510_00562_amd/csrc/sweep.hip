@@ -6,7 +6,9 @@
 //            feeds the threshold search (count and sum above a predicted
 //            window, values inside it), plus the FP64 partial sums of the
 //            stopping rule (eq. (28)).
-//   search   (select.hip): exact soft-threshold levels tau_s, tau_t.
+//   search   (select.hip, fallback.hip): exact soft-threshold levels tau_s,
+//            tau_t from the window candidates, or, for a window that
+//            missed, from three histogram passes in the same slot.
 //   sweep B  (pointwise): steps 2, 3, 7, 8, 13, the rest of step 14 and the
 //            FP64 partial sums of the l2-ball distance of step 15.
 //   finalize (one block): the l2-ball factor of step 15 (applied lazily when
