@@ -692,10 +692,15 @@ __global__ __launch_bounds__(NPT) void k_sweep_b(Table<DT> cubes, LaunchShape sh
 {
     __shared__ double red[NPT / 64];
     __shared__ int cube_of_block;
-    if (threadIdx.x == 0) {  // blocks [b0, b0 + nb) belong to one cube
-        int c = 0;
-        while (c + 1 < sh.ncubes && cubes[c + 1].c.b0 <= (int)blockIdx.x) ++c;
-        cube_of_block = c;
+    // blocks [b0, b0 + nb) belong to one cube: the last cube whose b0 is at
+    // most this block's index, found by one wavefront (one load per lane;
+    // a scan by one thread took a memory round trip per cube of a batch)
+    static_assert(kMaxBatch <= 64, "one wavefront covers the cubes");
+    if (threadIdx.x < 64) {
+        const int c = threadIdx.x;
+        const bool le = c < sh.ncubes && cubes[c].c.b0 <= (int)blockIdx.x;
+        const unsigned long long m = __ballot(le);
+        if (c == 0) cube_of_block = 63 - __clzll((long long)m);  // cube 0 starts at block 0
     }
     __syncthreads();
     const CubeArgs<DT> &a = cubes[__builtin_amdgcn_readfirstlane(cube_of_block)];
