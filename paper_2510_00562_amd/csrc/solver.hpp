@@ -352,11 +352,13 @@ struct LaunchShape {
     int b_kinds;      // sweep B forms present: 1 one or two columns per thread, 2 four
 };
 
-// Columns per sweep B thread for a row length: four when the row splits into
-// 16-byte groups (FP32 state), else two when it is even, else one.
+// Columns per sweep B thread for a row length: four when it is a multiple of
+// 4 (16-byte FP32 and 8-byte BF16 accesses), else two when it is even, else
+// one. dual_bytes: storage of the duals (the same rule for both).
 __host__ __device__ inline int sweep_b_cpt(int n2, int dual_bytes)
 {
-    return (n2 & 1) ? 1 : ((n2 & 3) == 0 && dual_bytes == 4 ? 4 : 2);
+    (void)dual_bytes;
+    return (n2 & 1) ? 1 : ((n2 & 3) == 0 ? 4 : 2);
 }
 
 // Host image of one cube's table entry (FP32 or BF16 duals: same size).

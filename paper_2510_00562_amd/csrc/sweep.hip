@@ -1084,9 +1084,8 @@ hipError_t slot_t(const void *table, const LaunchShape &sh, hipStream_t st, hipE
     if (nev >= 4) (void)hipEventRecord(ev[2], st);
     if (sh.b_kinds & 1)
         hipLaunchKernelGGL((k_sweep_b<DT, false>), dim3(sh.total_b), dim3(NPT), 0, st, cubes, sh);
-    if constexpr (sizeof(DT) == 4)  // four columns per thread with FP32 state only
-        if (sh.b_kinds & 2)
-            hipLaunchKernelGGL((k_sweep_b<DT, true>), dim3(sh.total_b), dim3(NPT), 0, st, cubes, sh);
+    if (sh.b_kinds & 2)
+        hipLaunchKernelGGL((k_sweep_b<DT, true>), dim3(sh.total_b), dim3(NPT), 0, st, cubes, sh);
     hipLaunchKernelGGL(k_finalize, dim3(sh.ncubes), dim3(NPT), 0, st, (const char *)table, stride);
     if (nev >= 4) (void)hipEventRecord(ev[3], st);
     return hipGetLastError();
