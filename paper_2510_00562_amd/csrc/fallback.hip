@@ -5,7 +5,8 @@
 // Each launch is a no-op (its blocks read one flag of the launch and leave)
 // unless the window search of this slot left a field of some working cube
 // pending. The blocks then split the voxels of the cubes with a pending
-// field evenly, evaluate z_s and z_t from the state exactly as sweep A does
+// field evenly, read z_s and z_t where sweep A stored them in this
+// iteration, or else evaluate them from the state exactly as sweep A does
 // (the same rounding operations, so the values are bit-identical), keep the
 // values whose higher bits match the bins the earlier levels chose, and add
 // them to LDS histograms that are flushed into the cube's global histogram
