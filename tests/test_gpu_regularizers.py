@@ -289,3 +289,43 @@ def test_four_voxel_kernels_match_the_one_voxel_kernels(variant):
     for k in STATE:
         e = rel_l2(states[0][k], states[1][k])
         assert e <= 1e-6, (k, e)
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_benchmark_cube_in_the_bench_configuration(ora, variant):
+    """The 256 x 256 x 128 benchmark cube (the four-voxel kernels, the grids
+    bench.py times): one step from a random state, every array within 1e-6
+    of the oracle, then 20 iterations from the initial point (u within
+    1e-5, the rest within 1e-4) and the thresholds of the last one."""
+    from synth.cubes import CUBE_256x256x128
+    c = make_cube(CUBE_256x256x128)
+    v = f32(c["v"])
+    shape = v.shape
+    announce(f"{NAMES[variant]}: benchmark cube {shape}")
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=c["omega"])
+    st = random_vstate(shape, variant, 17)
+    geo, dims, p, ws, vd = gpu_solver(shape, v, prm, variant)
+    for name in STATE:
+        geo.geo_state_set(dims, p, ws, name, vd, dev(st[name]))
+    res = geo.geo_step(dims, p, vd, ws, 1)
+    S = ora.VariantSolver(v, prm["eps"], prm["alpha"], prm["beta"], variant, omega=prm["omega"],
+                          state=st)
+    S.step(1)
+    g = get_state(geo, dims, p, ws, vd, shape, variant)
+    errs = {k: rel_l2(g[k], S.state[k]) for k in STATE}
+    print(f"{NAMES[variant]} one step: " + ", ".join(f"{k} {e:.1e}" for k, e in errs.items()), flush=True)
+    assert max(errs.values()) <= 1e-6, errs
+    assert res.r == pytest.approx(S.trace[-1][1], rel=1e-6)
+    del g, S, st
+    geo.geo_state_init(dims, p, vd, ws)
+    n = 20
+    res = geo.geo_step(dims, p, vd, ws, n)
+    S = ora.VariantSolver(v, prm["eps"], prm["alpha"], prm["beta"], variant, omega=prm["omega"])
+    S.step(n)
+    g = get_state(geo, dims, p, ws, vd, shape, variant)
+    errs = {k: rel_l2(g[k], S.state[k]) for k in STATE if np.linalg.norm(S.state[k]) > 0}
+    print(f"{NAMES[variant]} after {n}: " + ", ".join(f"{k} {e:.1e}" for k, e in errs.items()),
+          flush=True)
+    assert errs["u"] <= 1e-5 and max(errs.values()) <= 1e-4, errs
+    rel, r, ts, tt = S.trace[-1]
+    assert res.tau_s == pytest.approx(ts, rel=1e-5) and res.tau_t == pytest.approx(tt, rel=1e-5)
