@@ -205,33 +205,44 @@ constexpr double kWindowFillCalm = 4096.0;
 constexpr uint32_t kCalmNarrow = 8;
 
 // Window of |z| that sweep A collects for the next iteration. tau is
-// extrapolated linearly from the last two levels, and the half-width is
-// twice the error the same extrapolation made for this iteration (plus
-// 5e-5 tau, and never less than the last step plus 2e-4 tau when the
-// history is short or the prediction failed). Three times the error plus
-// 2e-4 tau held as well in steady state, with windows a third wider: the
-// 512 x 512 x 224 search took 89 instead of 51 us. budget > 0 and the density of |z| near
-// tau known from this iteration: the window is widened to hold about
-// kWindowFill values (the search's cost is flat up to there, and a wider
-// window misses less) and narrowed to hold at most about `budget` (a window
-// of hundreds of thousands of candidates costs the search more than the
-// histogram passes that a miss costs).
+// extrapolated from the last levels: quadratically once four are known (the
+// levels follow a smooth path after the first iterations, and the quadratic
+// error is a fraction of the linear one there), linearly from two or three.
+// The half-width is twice the error the same extrapolation made for this
+// iteration (plus 5e-5 tau, and never less than the last step plus 2e-4 tau
+// when the history is short or the prediction failed). Three times the
+// error plus 2e-4 tau held as well in steady state, with windows a third
+// wider: the 512 x 512 x 224 search took 89 instead of 51 us. budget > 0
+// and the density of |z| near tau known from this iteration: the window is
+// widened to hold about `fill` values (the search's cost is flat up to
+// there, and a wider window misses less) and narrowed to hold at most about
+// `budget` (a window of hundreds of thousands of candidates costs the search
+// more than the histogram passes that a miss costs).
 __device__ inline void set_window(SelState &o, bool missed, double budget, double fill = kWindowFill)
 {
     const double tau = o.tau;
     if (!(tau > 0.0) || !isfinite(tau)) {
         o.win_on = 0u;
+        o.tau_prev3 = 0.0;
         o.tau_prev2 = 0.0;
         o.tau_prev = tau;
         return;
     }
-    const double t1 = o.tau_prev, t2 = o.tau_prev2;
+    const double t1 = o.tau_prev, t2 = o.tau_prev2, t3 = o.tau_prev3;
     const bool h1 = t1 > 0.0 && isfinite(t1), h2 = h1 && t2 > 0.0 && isfinite(t2);
+    const bool h3 = h2 && t3 > 0.0 && isfinite(t3);
     const double step = h1 ? tau - t1 : 0.05 * tau;
-    const double err = h2 ? fabs(tau - (2.0 * t1 - t2)) : fabs(step);
+    double c = tau + (h1 ? step : 0.0);
+    double err = h2 ? fabs(tau - (2.0 * t1 - t2)) : fabs(step);
+    if (h3) {
+        const double cq = 3.0 * (tau - t1) + t2;
+        if (cq > 0.0) {
+            c = cq;
+            err = fabs(tau - (3.0 * (t1 - t2) + t3));
+        }
+    }
     double h = 2.0 * err + 5e-5 * tau;
     if (!h2 || missed) h = fmax(h, fabs(step) + 2e-4 * tau);
-    const double c = tau + (h1 ? step : 0.0);
     if (budget > 0.0 && o.dens > 0.0) {
         // as wide as the search's flat cost allows, narrower than the budget
         h = fmax(h, fill / (2.0 * o.dens));
@@ -242,6 +253,7 @@ __device__ inline void set_window(SelState &o, bool missed, double budget, doubl
     o.win_lo = __double2float_rd(lo);
     o.win_hi = __double2float_ru(hi);
     o.win_on = 1u;
+    o.tau_prev3 = h2 ? t2 : 0.0;
     o.tau_prev2 = h1 ? t1 : 0.0;
     o.tau_prev = tau;
 }

@@ -51,6 +51,7 @@ __global__ __launch_bounds__(kSelThreads) void k_select_begin(SelState *sel, int
         s.tau = s.radius <= 0.0 ? __longlong_as_double(0x7ff0000000000000ll) : 0.0;
         s.tau_prev = 0.0;
         s.tau_prev2 = 0.0;
+        s.tau_prev3 = 0.0;
         s.full = 1u;
         s.win_lo = s.win_hi = 0.f;
         s.win_on = 0u;
@@ -173,10 +174,11 @@ __global__ __launch_bounds__(kSelThreads) void k_select_level(SelState *sel, His
 constexpr int kWinThreads = 1024;
 constexpr int kWinBins = 1024;
 constexpr int kCandLds = 28672;  // candidates staged in LDS (112 KB); more are streamed
-// More candidates than kCandLds are streamed through LDS in chunks of kChunk
-// at every radix level. In the pass whose range holds at most kComp of
-// them, the ones in range are also compacted into the first kComp entries,
-// and the following levels read only those.
+// More candidates than kCandLds are streamed through LDS at every radix
+// level, kCandLds at a time. In the pass whose range holds at most kComp of
+// them, the ones in range are also compacted into the first kComp entries
+// (that pass streams kChunk at a time), and the following levels read only
+// those.
 constexpr int kChunk = 16384;
 constexpr int kComp = kCandLds - kChunk;
 
@@ -573,12 +575,15 @@ __global__ __launch_bounds__(kWinThreads) void k_select_window(const char *table
                 }
             }
         } else {
-            // stream the candidates through LDS, kChunk at a time in flat
+            // stream the candidates through LDS, a chunk at a time in flat
             // order, then every thread bins the chunk
             if (tid == 0) ncomp = 0u;
-            float *chunk = cl + kComp;
-            for (int c0 = 0; c0 < total; c0 += kChunk) {
-                const int c1 = c0 + kChunk < total ? c0 + kChunk : total;
+            // a pass that also compacts keeps the first kComp entries for
+            // them; otherwise the chunks take the whole staging area
+            float *chunk = compact ? cl + kComp : cl;
+            const int csz = compact ? kChunk : kCandLds;
+            for (int c0 = 0; c0 < total; c0 += csz) {
+                const int c1 = c0 + csz < total ? c0 + csz : total;
                 __syncthreads();  // the previous chunk has been binned
                 if (own)
                     copy_own(c0, c1, chunk);

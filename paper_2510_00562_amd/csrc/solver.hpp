@@ -24,6 +24,7 @@ struct SelState {
     double tau;        // soft-threshold level of this iteration
     double tau_prev;   // level of the previous iteration (window prediction)
     double tau_prev2;  // and of the one before
+    double tau_prev3;  // and of the one before that
     uint64_t c_above;  // radix search: count of those values
     uint32_t prefix;   // radix search: pattern bits fixed so far
     uint32_t done;     // tau final for this iteration

@@ -956,6 +956,7 @@ __global__ void k_state_loaded(DevScalars *sc, int var)
             sc->sel[f].win_on = 0u;
             sc->sel[f].tau_prev = 0.0;
             sc->sel[f].tau_prev2 = 0.0;
+            sc->sel[f].tau_prev3 = 0.0;
             sc->sel[f].done = 1u;
         }
         sc->zstore = 1u;

@@ -5,7 +5,7 @@ where the threshold moves fast.
 Two kinds of iteration are pinned against the FP64 oracle:
   * windows holding more values than fit in LDS at once (the search streams
     them through LDS in chunks and compacts a deeper radix level): cubes
-    large enough that the candidate budget of a window (N/128) exceeds what
+    large enough that the candidate budget of a window (N/256) exceeds what
     LDS holds;
   * windows that miss (the first iterations after the threshold leaves 0):
     the three histogram passes of the same launch slot find the threshold,
