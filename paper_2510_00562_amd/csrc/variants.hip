@@ -41,15 +41,15 @@ namespace geo {
 
 namespace {
 
-// The primal kernel's blocks are the search's tiles: at most 1024 blocks of
-// 1024 threads (two per CU at full occupancy), so that the window search
-// scans few tile counts (with 4096 blocks of 256 threads it took 43 instead
-// of 32 us). The dual kernel runs up to 8192 blocks of 256 threads (228
-// instead of 165 us with 2048 blocks of 1024).
-constexpr int VT = 1024;          // primal, init and copy kernels
-constexpr int VTP4 = 512;         // primal kernel, four voxels per thread (68 VGPRs: three blocks per CU)
+// The primal kernel's blocks are the search's tiles: few of them, so that
+// the window search scans few slices (with 4096 blocks of 256 threads it
+// took 43 instead of 32 us), and no more than the device holds at once
+// (primal_grid). The dual kernel runs up to 8192 blocks of 256 threads (228
+// instead of 165 us with 2048 blocks of 1024; 4096 blocks: 2% slower).
+constexpr int VT = 1024;          // init and copy kernels
+constexpr int VTP = 512;          // primal kernels (68 VGPRs four voxels per thread, 56 one)
 constexpr int VTD = 256;          // dual kernel
-constexpr int kVarTiles = 1024;   // primal kernel blocks (tiles of the window search)
+constexpr int kVarTiles = 768;    // most primal kernel blocks (the workspace regions of the tiles)
 constexpr int kVarBBlocks = 8192; // dual kernel blocks
 
 __device__ __forceinline__ float soft_d(float z, double tau)
@@ -119,9 +119,9 @@ __device__ __forceinline__ void block_sum8v(double (&x)[8], double *red /* 8 * N
         }
 }
 
-__global__ __launch_bounds__(VT) void k_var_primal(VarArgs a)
+__global__ __launch_bounds__(VTP) void k_var_primal(VarArgs a)
 {
-    __shared__ double red[8 * (VT / 64)];
+    __shared__ double red[8 * (VTP / 64)];
     __shared__ uint32_t ncand[2];
     DevScalars *sc = a.sc;
     if (idle(sc)) return;
@@ -146,7 +146,7 @@ __global__ __launch_bounds__(VT) void k_var_primal(VarArgs a)
     float c_hi[2] = {0.f, 0.f};
     // the same trip count for every lane of the block, so that whole
     // wavefronts append candidates
-    for (int64_t q0 = (int64_t)b * VT; q0 < N; q0 += (int64_t)nt * VT) {
+    for (int64_t q0 = (int64_t)b * VTP; q0 < N; q0 += (int64_t)nt * VTP) {
         const int64_t q = q0 + tid;
         const bool in = q < N;
         float z[2] = {0.f, 0.f};
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(VT) void k_var_primal(VarArgs a)
         }
     }
     double acc[8] = {du2, u2, (double)c_hi[0], s_hi[0], s_all[0], (double)c_hi[1], s_hi[1], s_all[1]};
-    block_sum8v<VT>(acc, red);
+    block_sum8v<VTP>(acc, red);
     if (tid == 0) {
         a.ccount[b] = ncand[0];
         a.ccount[nt + b] = ncand[1];
@@ -244,9 +244,9 @@ __device__ __forceinline__ void dT4(const Dims &d, const float *pv, const float 
     }
 }
 
-__global__ __launch_bounds__(VTP4) void k_var_primal4(VarArgs a)
+__global__ __launch_bounds__(VTP) void k_var_primal4(VarArgs a)
 {
-    __shared__ double red[8 * (VTP4 / 64)];
+    __shared__ double red[8 * (VTP / 64)];
     __shared__ uint32_t ncand[2];
     DevScalars *sc = a.sc;
     if (idle(sc)) return;
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(VTP4) void k_var_primal4(VarArgs a)
     __syncthreads();  // ncand cleared
     double du2 = 0.0, u2 = 0.0, s_hi[2] = {0.0, 0.0}, s_all[2] = {0.0, 0.0};
     float c_hi[2] = {0.f, 0.f};
-    for (int64_t g0 = (int64_t)b * VTP4; g0 < Q; g0 += (int64_t)nt * VTP4) {
+    for (int64_t g0 = (int64_t)b * VTP; g0 < Q; g0 += (int64_t)nt * VTP) {
         const int64_t g = g0 + tid;
         const bool in = g < Q;
         float z[2][4] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
@@ -331,7 +331,7 @@ __global__ __launch_bounds__(VTP4) void k_var_primal4(VarArgs a)
             }
     }
     double acc[8] = {du2, u2, (double)c_hi[0], s_hi[0], s_all[0], (double)c_hi[1], s_hi[1], s_all[1]};
-    block_sum8v<VTP4>(acc, red);
+    block_sum8v<VTP>(acc, red);
     if (tid == 0) {
         a.ccount[b] = ncand[0];
         a.ccount[nt + b] = ncand[1];
@@ -597,30 +597,63 @@ int grid_of(int64_t n, int cap, int threads = VT)
 
 size_t align256v(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Blocks of `kernel` that the device holds at once (queried once per kernel).
+template <typename K>
+int resident_blocks(K kernel, int threads)
+{
+    int dev = 0, cus = 256, per = 1;
+    if (hipGetDevice(&dev) == hipSuccess) {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, dev) == hipSuccess) cus = prop.multiProcessorCount;
+    }
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, threads, 0) != hipSuccess || per < 1)
+        per = 1;
+    return cus * per;
+}
+
+// Primal kernel blocks for N voxels: enough for one voxel (or group of four)
+// per thread, at most what the device holds at once (three blocks per CU of
+// the four-voxel kernel, four of the one-voxel kernel) and kVarTiles (three
+// per CU of 256), so that the grid runs in one round: 1024 blocks of the
+// four-voxel kernel left a second round of 256 (iterations 2.4% (HSSTV2)
+// and 3.2% (SSTV) slower than with 768; with 512, 1.2% and 2.4%). The
+// workspace regions of the tiles sized for 1024 instead of 768 moved the
+// arrays after them and made the dual kernel 2% slower.
+int primal_grid(int64_t N, bool quads)
+{
+    static const int res1 = resident_blocks(k_var_primal, VTP), res4 = resident_blocks(k_var_primal4, VTP);
+    const int cap = quads ? res4 : res1;
+    return grid_of(quads ? N / 4 : N, cap < kVarTiles ? cap : kVarTiles, VTP);
+}
+
+// four voxels per thread when rows split into whole 16-byte groups and v is
+// 16-byte aligned (the workspace arrays are 256-byte aligned)
+bool use_quads(const Dims &d, const float *v) { return d.n2 % 4 == 0 && ((uintptr_t)v & 15u) == 0; }
+
 // Workspace: the scalars, the search's regions, the launch table, then the
 // N-float arrays.
 struct VarLayout {
     size_t sc, part, winpart, hist, rec, cand, ccount, table, u0, u1, t0, t1, s, y1, y3, q, z, total;
-    int ntiles, nb;
-    int64_t cap;  // candidates per field
+    int max_tiles, nb;  // most primal blocks, dual blocks
+    int64_t cap;        // candidates per field
 };
 
 VarLayout var_layout(int64_t N, int P)
 {
     VarLayout L;
-    L.ntiles = grid_of(N, kVarTiles);
+    L.max_tiles = grid_of(N, kVarTiles, VTP);
     L.nb = grid_of(N, kVarBBlocks, VTD);
     L.cap = N / 16 > 65536 ? N / 16 : 65536;
     size_t o = 0;
     auto take = [&](size_t b) { const size_t at = o; o = align256v(o + b); return at; };
     const size_t f = sizeof(float) * (size_t)N;
     L.sc = take(sizeof(DevScalars));
-    L.part = take(sizeof(double) * (2 * (size_t)L.ntiles + (size_t)L.nb));
-    L.winpart = take(sizeof(double) * 2 * 3 * (size_t)L.ntiles);
+    L.part = take(sizeof(double) * (2 * (size_t)L.max_tiles + (size_t)L.nb));
+    L.winpart = take(sizeof(double) * 2 * 3 * (size_t)L.max_tiles);
     L.hist = take(6 * sizeof(Hist));  // 3 radix levels x 2 fields
     L.rec = take(6 * sizeof(FbRec));
     L.cand = take(sizeof(float) * 2 * (size_t)L.cap);
-    L.ccount = take(sizeof(uint32_t) * 2 * (size_t)L.ntiles);
+    L.ccount = take(sizeof(uint32_t) * 2 * (size_t)L.max_tiles);
     L.table = take(table_bytes(1));
     L.u0 = take(f);
     L.u1 = take(f);
@@ -668,9 +701,10 @@ VarArgs var_args(const Dims &d, const geo_params *p, const float *v, void *ws, V
     a.y3 = (float *)(b + L.y3);
     a.q = (float *)(b + L.q);
     a.z = (float *)(b + L.z);
-    a.ntiles = L.ntiles;
+    // the primal grid (at most max_tiles: both forms need at most N / VTP)
+    a.ntiles = primal_grid(d.plane, v && use_quads(d, v));
     a.nb = L.nb;
-    a.capt = (int)(L.cap / L.ntiles);
+    a.capt = (int)(L.cap / a.ntiles);
     return a;
 }
 
@@ -748,9 +782,7 @@ hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws
         ev.resize(2 * (size_t)(all ? n_iter : n_iter / kTimedEvery));
         for (size_t k = 0; k < ev.size() && e == hipSuccess; ++k) e = hipEventCreate(&ev[k]);
     }
-    // four voxels per thread when rows split into whole 16-byte groups and v
-    // is 16-byte aligned (the workspace arrays are 256-byte aligned)
-    const bool quads = d.n2 % 4 == 0 && ((uintptr_t)v & 15u) == 0;
+    const bool quads = use_quads(d, v);
     // with a tolerance the host reads the stop flag every check_every slots
     const int every = p->tol > 0.0 ? (p->check_every > 0 ? p->check_every : 32) : (n_iter > 0 ? n_iter : 1);
     size_t ne = 0;
@@ -760,9 +792,9 @@ hipError_t var_step(const Dims &d, const geo_params *p, const float *v, void *ws
         const int batch = n_iter - issued < every ? n_iter - issued : every;
         for (int it = issued; it < issued + batch && e == hipSuccess; ++it) {
             if (quads)
-                hipLaunchKernelGGL(k_var_primal4, dim3(a.ntiles), dim3(VTP4), 0, st, a);
+                hipLaunchKernelGGL(k_var_primal4, dim3(a.ntiles), dim3(VTP), 0, st, a);
             else
-                hipLaunchKernelGGL(k_var_primal, dim3(a.ntiles), dim3(VT), 0, st, a);
+                hipLaunchKernelGGL(k_var_primal, dim3(a.ntiles), dim3(VTP), 0, st, a);
             e = launch_select_window(table, stride, 1, 0, st);
             for (int level = 0; level < 3 && e == hipSuccess; ++level)
                 e = launch_fallback(table, 4, sh, level, st);
