@@ -610,9 +610,10 @@ def bench_regularizer(args):
     el = time.perf_counter() - t0
     K = args.steps
     value = N * K / el
-    # dual kernel, per voxel: reads z_s, z_t, s, t, u+, u, the P planes of
-    # y1, y3, the y4 residual and v; writes s, t+, y3, y1 and the residual
-    dual_bytes = 4 * (13 + 2 * P)
+    # dual kernel, per voxel: reads s, t, u+, u, the P planes of y1, y3, the
+    # y4 residual and v (z_s, z_t evaluated from them again); writes s, t+,
+    # y3, y1 and the residual
+    dual_bytes = 4 * (11 + 2 * P)
     # the iteration's state (u, s, t, y1, y3, y4) read and written once, v read
     iter_bytes = 2 * 4 * (5 + P) + 4
     avg_s = dual_ms / K / 1e3

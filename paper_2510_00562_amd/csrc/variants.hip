@@ -19,11 +19,14 @@
 //                  candidates and the FP64 partials of the stopping rule;
 //   window search and three histogram passes (select.hip, fallback.hip):
 //                  the exact thresholds tau_s, tau_t;
-//   dual kernel:   s+, t+ (soft thresholds), the extrapolations x' = 2 x+ - x,
-//                  y1 += g_y A u' and the conjugate prox of the regularizer
-//                  (a clip to [-1, 1], or each 4-entry group scaled into the
-//                  unit l2 ball), y3 += g_y D_v t', the y4 residual and FP64
-//                  partials of its norm;
+//   dual kernel:   s+, t+ (soft thresholds of z_s, z_t, evaluated again from
+//                  the state with the primal kernel's operations: y3 and the
+//                  y4 residual are ping-ponged, so the rows next to a voxel
+//                  still hold their old values), the extrapolations
+//                  x' = 2 x+ - x, y1 += g_y A u' and the conjugate prox of the
+//                  regularizer (a clip to [-1, 1], or each 4-entry group
+//                  scaled into the unit l2 ball), y3 += g_y D_v t', the y4
+//                  residual and FP64 partials of its norm;
 //   finalize (sweep.hip): the fidelity-ball factor (y4 - g_y P_B(y4/g_y) =
 //                  c g_y (y4/g_y - v), c = max(0, 1 - eps/r), applied when y4
 //                  is next read), the relative change, the stopping rule, the
@@ -66,8 +69,9 @@ struct VarArgs {
     const float *v;
     DevScalars *sc;
     float *u[2], *t[2];       // ping-pong by iteration parity
-    float *s, *y1, *y3, *q;
-    float *z;                 // [2][N]: z_s, z_t
+    float *y3[2], *q[2];      // also (the dual kernel reads the rows next to its own)
+    float *s, *y1;
+    float *z;                 // [2][N]: z_s, z_t (read by the histogram passes)
     double *part;             // [2 * ntiles] primal partials, then [nb] of r^2
     double *winpart;          // [2][ntiles][3]
     float *cand;              // [2][ntiles][capt]
@@ -96,6 +100,24 @@ __device__ __forceinline__ float dT(const Dims &d, const float *pv, const float 
     if (j >= 1) a += ph[q - 1];
     if (j <= d.n2 - 2) a -= ph[q];
     return a;
+}
+
+// The inputs z_s = s - y4 and z_t = t - g_t (D_v^T y3 + y4) of the two
+// l1-ball projections at a voxel of row i, y4 = a4 q, from the loaded
+// values y3m = y3(i - 1) and y3c = y3(i) (the rows that do not exist are
+// masked here). Both kernels evaluate them with these operations, so the
+// dual kernel's values are the primal kernel's bit for bit.
+__device__ __forceinline__ float var_dvt(int i, int n1, float y3m, float y3c)
+{
+    float x = 0.f;
+    if (i >= 1) x += y3m;
+    if (i <= n1 - 2) x -= y3c;
+    return x;
+}
+__device__ __forceinline__ float var_zs(float s, float y4) { return s - y4; }
+__device__ __forceinline__ float var_zt(float t, float dvt, float y4, float gt)
+{
+    return __builtin_fmaf(-gt, dvt + y4, t);
 }
 
 // Sums of 8 FP64 values over a block of NT threads in a fixed order; valid
@@ -130,7 +152,7 @@ __global__ __launch_bounds__(VTP) void k_var_primal(VarArgs a)
     const int tid = threadIdx.x, b = blockIdx.x, nt = a.ntiles;
     if (tid < 2) ncand[tid] = 0u;
     const int par = (int)(sc->iter & 1u);
-    const float *u = a.u[par], *t = a.t[par];
+    const float *u = a.u[par], *t = a.t[par], *y3 = a.y3[par], *qo = a.q[par];
     float *un = a.u[par ^ 1];
     const float a4 = (float)sc->a4;
     const float *y1v = a.y1, *y1h = a.y1 + N;
@@ -158,16 +180,14 @@ __global__ __launch_bounds__(VTP) void k_var_primal(VarArgs a)
             if (k >= 1) g += dT(d, y1v, y1h, k - 1, i, j);
             if (k <= d.n3 - 2) g -= dT(d, y1v, y1h, k, i, j);
             if (a.P == 4) g += a.omega * dT(d, a.y1 + 2 * N, a.y1 + 3 * N, k, i, j);
-            const float y4 = a4 * a.q[q];
+            const float y4 = a4 * qo[q];
             const float uo = u[q];
             const float x = uo - a.gu * (g + y4);
             const float nu = fminf(fmaxf(x, a.mu_lo), a.mu_hi);
             un[q] = nu;
-            float dvt = 0.f;  // (D_v^T y3)(k, i, j)
-            if (i >= 1) dvt += a.y3[q - d.n2];
-            if (i <= d.n1 - 2) dvt -= a.y3[q];
-            z[0] = a.s[q] - y4;
-            z[1] = t[q] - a.gt * (dvt + y4);
+            const float y3m = i >= 1 ? y3[q - d.n2] : 0.f, y3c = i <= d.n1 - 2 ? y3[q] : 0.f;
+            z[0] = var_zs(a.s[q], y4);
+            z[1] = var_zt(t[q], var_dvt(i, d.n1, y3m, y3c), y4, a.gt);
             a.z[q] = z[0];
             a.z[N + q] = z[1];
             const double dl = (double)nu - (double)uo;
@@ -255,7 +275,7 @@ __global__ __launch_bounds__(VTP) void k_var_primal4(VarArgs a)
     const int tid = threadIdx.x, b = blockIdx.x, nt = a.ntiles;
     if (tid < 2) ncand[tid] = 0u;
     const int par = (int)(sc->iter & 1u);
-    const float *u = a.u[par], *t = a.t[par];
+    const float *u = a.u[par], *t = a.t[par], *y3 = a.y3[par], *qo = a.q[par];
     float *un = a.u[par ^ 1];
     const float a4 = (float)sc->a4;
     const float *y1v = a.y1, *y1h = a.y1 + N;
@@ -281,10 +301,10 @@ __global__ __launch_bounds__(VTP) void k_var_primal4(VarArgs a)
             if (k >= 1) dT4(d, y1v, y1h, k - 1, i, j0, gm);
             if (k <= d.n3 - 2) dT4(d, y1v, y1h, k, i, j0, gk);
             if (a.P == 4) dT4(d, a.y1 + 2 * N, a.y1 + 3 * N, k, i, j0, go);
-            const F4 qv = ld4(a.q + q), uo = ld4(u + q), sv = ld4(a.s + q), tv = ld4(t + q);
+            const F4 qv = ld4(qo + q), uo = ld4(u + q), sv = ld4(a.s + q), tv = ld4(t + q);
             F4 y3m = {{0.f, 0.f, 0.f, 0.f}}, y3c = y3m;
-            if (i >= 1) y3m = ld4(a.y3 + q - d.n2);
-            if (i <= d.n1 - 2) y3c = ld4(a.y3 + q);
+            if (i >= 1) y3m = ld4(y3 + q - d.n2);
+            if (i <= d.n1 - 2) y3c = ld4(y3 + q);
             F4 nu, zs, zt;
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
@@ -295,11 +315,8 @@ __global__ __launch_bounds__(VTP) void k_var_primal4(VarArgs a)
                 const float y4 = a4 * qv.x[e];
                 const float x = uo.x[e] - a.gu * (gg + y4);
                 nu.x[e] = fminf(fmaxf(x, a.mu_lo), a.mu_hi);
-                float dvt = 0.f;
-                if (i >= 1) dvt += y3m.x[e];
-                if (i <= d.n1 - 2) dvt -= y3c.x[e];
-                zs.x[e] = sv.x[e] - y4;
-                zt.x[e] = tv.x[e] - a.gt * (dvt + y4);
+                zs.x[e] = var_zs(sv.x[e], y4);
+                zt.x[e] = var_zt(tv.x[e], var_dvt(i, d.n1, y3m.x[e], y3c.x[e]), y4, a.gt);
                 z[0][e] = zs.x[e];
                 z[1][e] = zt.x[e];
                 const double dl = (double)nu.x[e] - (double)uo.x[e];
@@ -358,27 +375,36 @@ __global__ __launch_bounds__(VTD) void k_var_dual(VarArgs a)
     const int64_t N = d.plane;
     const int par = (int)(sc->iter & 1u);
     const float *uo = a.u[par], *un = a.u[par ^ 1], *to = a.t[par];
-    float *tn = a.t[par ^ 1];
+    const float *y3o = a.y3[par], *qo = a.q[par];
+    float *tn = a.t[par ^ 1], *y3n = a.y3[par ^ 1], *qn = a.q[par ^ 1];
     // the thresholds: from the window search, or from this slot's passes
     const double ts = sc->sel[0].done ? sc->sel[0].tau : fb_final(a.rec, 0).tau;
     const double tt = sc->sel[1].done ? sc->sel[1].tau : fb_final(a.rec, 1).tau;
     const float a4 = (float)sc->a4;
-    const float *zs = a.z, *zt = a.z + N;
     double r2 = 0.0;
     for (int64_t q = (int64_t)blockIdx.x * VTD + threadIdx.x; q < N; q += (int64_t)gridDim.x * VTD) {
         int k, i, j;
         coords(d, q, k, i, j);
-        const float so = a.s[q], sn = soft_d(zs[q], ts);
+        // z_s, z_t here as the primal kernel evaluated them
+        const float y4 = a4 * qo[q], y3c = y3o[q];
+        const float y3m = i >= 1 ? y3o[q - d.n2] : 0.f;
+        const float so = a.s[q], sn = soft_d(var_zs(so, y4), ts);
         a.s[q] = sn;
         const float sp = 2.f * sn - so;
-        const float tq = soft_d(zt[q], tt);
+        const float tq = soft_d(var_zt(to[q], var_dvt(i, d.n1, y3m, y3c), y4, a.gt), tt);
         tn[q] = tq;
         const float tp = 2.f * tq - to[q];
-        // y3 += g_y D_v t' (t' one row down from its own z_t and old t)
+        // y3 += g_y D_v t' (t' one row down from its own z_t and old t); the
+        // last row keeps its value
+        float y3x = y3c;
         if (i <= d.n1 - 2) {
-            const float tp1 = 2.f * soft_d(zt[q + d.n2], tt) - to[q + d.n2];
-            a.y3[q] += a.gy * (tp1 - tp);
+            const int64_t qd = q + d.n2;
+            const float y4d = a4 * qo[qd], y3d = i + 1 <= d.n1 - 2 ? y3o[qd] : 0.f;
+            const float ztd = var_zt(to[qd], var_dvt(i + 1, d.n1, y3c, y3d), y4d, a.gt);
+            const float tp1 = 2.f * soft_d(ztd, tt) - to[qd];
+            y3x = y3c + a.gy * (tp1 - tp);
         }
+        y3n[q] = y3x;
         // A u' here: D D_s u' on the edges that exist (and omega D u')
         const float u0 = uprime(d, un, uo, k, i, j);
         const bool ei = i <= d.n1 - 2, ej = j <= d.n2 - 2, ek = k <= d.n3 - 2;
@@ -409,9 +435,9 @@ __global__ __launch_bounds__(VTD) void k_var_dual(VarArgs a)
         for (int c = 0; c < 4; ++c)
             if (c < a.P) a.y1[c * N + q] = y[c];
         // y4'/g_y - v = (a4/g_y) q + u' + s' + t' - v
-        const float qn = (a4 / a.gy) * a.q[q] + ((u0 + sp) + tp) - a.v[q];
-        a.q[q] = qn;
-        r2 += (double)qn * (double)qn;
+        const float qx = (a4 / a.gy) * qo[q] + ((u0 + sp) + tp) - a.v[q];
+        qn[q] = qx;
+        r2 += (double)qx * (double)qx;
     }
     const double tot = block_sum<VTD>(r2, red);
     if (threadIdx.x == 0) a.part[2 * a.ntiles + blockIdx.x] = tot;
@@ -437,39 +463,48 @@ __global__ __launch_bounds__(VTD) void k_var_dual4(VarArgs a)
     const int64_t N = d.plane, Q = N / 4;
     const int par = (int)(sc->iter & 1u);
     const float *uo = a.u[par], *un = a.u[par ^ 1], *to = a.t[par];
-    float *tn = a.t[par ^ 1];
+    const float *y3o = a.y3[par], *qo = a.q[par];
+    float *tn = a.t[par ^ 1], *y3n = a.y3[par ^ 1], *qw = a.q[par ^ 1];
     const double ts = sc->sel[0].done ? sc->sel[0].tau : fb_final(a.rec, 0).tau;
     const double tt = sc->sel[1].done ? sc->sel[1].tau : fb_final(a.rec, 1).tau;
     const float a4 = (float)sc->a4;
-    const float *zs = a.z, *zt = a.z + N;
     double r2 = 0.0;
     for (int64_t g = (int64_t)blockIdx.x * VTD + threadIdx.x; g < Q; g += (int64_t)gridDim.x * VTD) {
         const int64_t q = 4 * g;
         int k, i, j0;
         coords(d, q, k, i, j0);
         const bool ei = i <= d.n1 - 2, ek = k <= d.n3 - 2;
-        const F4 zsv = ld4(zs + q), ztv = ld4(zt + q), so = ld4(a.s + q), tov = ld4(to + q);
+        const F4 so = ld4(a.s + q), tov = ld4(to + q), qv = ld4(qo + q), y3c = ld4(y3o + q);
+        F4 y3m = {{0.f, 0.f, 0.f, 0.f}};
+        if (i >= 1) y3m = ld4(y3o + q - d.n2);
         F4 sn, tq, sp, tp;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-            sn.x[e] = soft_d(zsv.x[e], ts);
+            // z_s, z_t here as the primal kernel evaluated them
+            const float y4 = a4 * qv.x[e];
+            sn.x[e] = soft_d(var_zs(so.x[e], y4), ts);
             sp.x[e] = 2.f * sn.x[e] - so.x[e];
-            tq.x[e] = soft_d(ztv.x[e], tt);
+            tq.x[e] = soft_d(var_zt(tov.x[e], var_dvt(i, d.n1, y3m.x[e], y3c.x[e]), y4, a.gt), tt);
             tp.x[e] = 2.f * tq.x[e] - tov.x[e];
         }
         st4(a.s + q, sn);
         st4(tn + q, tq);
-        // y3 += g_y D_v t' (t' one row down from its own z_t and old t)
+        // y3 += g_y D_v t' (t' one row down from its own z_t and old t); the
+        // last row keeps its value
+        F4 y3x = y3c;
         if (ei) {
-            const F4 zd = ld4(zt + q + d.n2), td = ld4(to + q + d.n2);
-            F4 y3 = ld4(a.y3 + q);
+            const int64_t qd = q + d.n2;
+            const F4 td = ld4(to + qd), qd4 = ld4(qo + qd);
+            F4 y3d = {{0.f, 0.f, 0.f, 0.f}};
+            if (i + 1 <= d.n1 - 2) y3d = ld4(y3o + qd);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float tp1 = 2.f * soft_d(zd.x[e], tt) - td.x[e];
-                y3.x[e] += a.gy * (tp1 - tp.x[e]);
+                const float ztd = var_zt(td.x[e], var_dvt(i + 1, d.n1, y3c.x[e], y3d.x[e]), a4 * qd4.x[e], a.gt);
+                const float tp1 = 2.f * soft_d(ztd, tt) - td.x[e];
+                y3x.x[e] = y3c.x[e] + a.gy * (tp1 - tp.x[e]);
             }
-            st4(a.y3 + q, y3);
         }
+        st4(y3n + q, y3x);
         // u' on the rows (k, i), (k, i + 1), (k + 1, i), (k + 1, i + 1)
         F4 u0, ui = {{0.f, 0.f, 0.f, 0.f}}, uk = ui, uki = ui;
         float u0n, ukn = 0.f, dummy;
@@ -481,7 +516,7 @@ __global__ __launch_bounds__(VTD) void k_var_dual4(VarArgs a)
 #pragma unroll
         for (int c = 0; c < 4; ++c)
             if (c < a.P) yv[c] = ld4(a.y1 + c * N + q);
-        const F4 qv = ld4(a.q + q), vv = ld4(a.v + q);
+        const F4 vv = ld4(a.v + q);
         F4 qn;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -516,7 +551,7 @@ __global__ __launch_bounds__(VTD) void k_var_dual4(VarArgs a)
 #pragma unroll
         for (int c = 0; c < 4; ++c)
             if (c < a.P) st4(a.y1 + c * N + q, yv[c]);
-        st4(a.q + q, qn);
+        st4(qw + q, qn);
     }
     const double tot = block_sum<VTD>(r2, red);
     if (threadIdx.x == 0) a.part[2 * a.ntiles + blockIdx.x] = tot;
@@ -530,8 +565,8 @@ __global__ __launch_bounds__(VT) void k_var_init(VarArgs a, double eps, double t
         a.u[0][q] = a.v[q];
         a.t[0][q] = 0.f;
         a.s[q] = 0.f;
-        a.y3[q] = 0.f;
-        a.q[q] = 0.f;
+        a.y3[0][q] = 0.f;
+        a.q[0][q] = 0.f;
         for (int c = 0; c < a.P; ++c) a.y1[c * N + q] = 0.f;
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -578,8 +613,8 @@ __global__ __launch_bounds__(VT) void k_var_io(VarArgs a, int var, float *out, c
     case GEO_VAR_S: base = a.s; break;
     case GEO_VAR_T: base = a.t[par]; break;
     case GEO_VAR_Y1: base = a.y1; break;
-    case GEO_VAR_Y3: base = a.y3; break;
-    default: base = a.q; break;
+    case GEO_VAR_Y3: base = a.y3[par]; break;
+    default: base = a.q[par]; break;
     }
     for (int64_t g = (int64_t)blockIdx.x * VT + threadIdx.x; g < n; g += (int64_t)gridDim.x * VT) {
         if (out)
@@ -633,7 +668,7 @@ bool use_quads(const Dims &d, const float *v) { return d.n2 % 4 == 0 && ((uintpt
 // Workspace: the scalars, the search's regions, the launch table, then the
 // N-float arrays.
 struct VarLayout {
-    size_t sc, part, winpart, hist, rec, cand, ccount, table, u0, u1, t0, t1, s, y1, y3, q, z, total;
+    size_t sc, part, winpart, hist, rec, cand, ccount, table, u0, u1, t0, t1, s, y1, y3[2], q[2], z, total;
     int max_tiles, nb;  // most primal blocks, dual blocks
     int64_t cap;        // candidates per field
 };
@@ -661,8 +696,10 @@ VarLayout var_layout(int64_t N, int P)
     L.t1 = take(f);
     L.s = take(f);
     L.y1 = take((size_t)P * f);
-    L.y3 = take(f);
-    L.q = take(f);
+    L.y3[0] = take(f);
+    L.y3[1] = take(f);
+    L.q[0] = take(f);
+    L.q[1] = take(f);
     L.z = take(2 * f);
     L.total = o;
     return L;
@@ -698,8 +735,10 @@ VarArgs var_args(const Dims &d, const geo_params *p, const float *v, void *ws, V
     a.t[1] = (float *)(b + L.t1);
     a.s = (float *)(b + L.s);
     a.y1 = (float *)(b + L.y1);
-    a.y3 = (float *)(b + L.y3);
-    a.q = (float *)(b + L.q);
+    a.y3[0] = (float *)(b + L.y3[0]);
+    a.y3[1] = (float *)(b + L.y3[1]);
+    a.q[0] = (float *)(b + L.q[0]);
+    a.q[1] = (float *)(b + L.q[1]);
     a.z = (float *)(b + L.z);
     // the primal grid (at most max_tiles: both forms need at most N / VTP)
     a.ntiles = primal_grid(d.plane, v && use_quads(d, v));

@@ -202,7 +202,7 @@ def test_regularizer_argument_checks_without_gpu():
         p = geo.params(1.0, 1.0, 1.0, regularizer=reg)
         assert L.geo_workspace_size(geo.geo_dims(4096, 4096, 1), ctypes.byref(p), ctypes.byref(n)) == 0
         N = 4096 * 4096
-        assert n.value >= (9 + (2 if reg == 1 else 4)) * 4 * N  # 9 arrays + the planes of y1
+        assert n.value >= (11 + (2 if reg == 1 else 4)) * 4 * N  # 11 arrays + the planes of y1
         assert L.geo_workspace_size(geo.geo_dims(4, 5, 6), ctypes.byref(p), ctypes.byref(n)) == 0
         small = n.value
         assert L.geo_workspace_size(geo.geo_dims(0, 5, 6), ctypes.byref(p), ctypes.byref(n)) == -1
