@@ -194,10 +194,15 @@ __device__ __forceinline__ uint32_t lvl_exponent(int level, uint32_t prefix, int
 // device factor a (max(0, 1 - eps/||q||) / 5 after an iteration).
 __device__ __forceinline__ float y4_of(float q, float a) { return __fmul_rn(a, q); }
 __device__ __forceinline__ float zs_of(float s, float y4) { return __fsub_rn(s, y4); }
-// y3m = y3 at (i-1) (0 on the first row), y3c = y3 at i masked by m_v(i)
+// y3m = y3 at (i-1) (0 on the first row), y3c = y3 at i masked by m_v(i),
+// step the step size of t (1/3 here; 1/5 for the comparison regularizers)
+__device__ __forceinline__ float zt_of(float t, float y3m, float y3c, float y4, float step)
+{
+    return __fsub_rn(t, __fmul_rn(step, __fadd_rn(__fsub_rn(y3m, y3c), y4)));
+}
 __device__ __forceinline__ float zt_of(float t, float y3m, float y3c, float y4)
 {
-    return __fsub_rn(t, __fmul_rn(kStepT, __fadd_rn(__fsub_rn(y3m, y3c), y4)));
+    return zt_of(t, y3m, y3c, y4, kStepT);
 }
 
 }  // namespace geo

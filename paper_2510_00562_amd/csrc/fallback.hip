@@ -111,7 +111,7 @@ __global__ __launch_bounds__(kFbThreads) void k_fb_hist(const CubeArgs<DT> *__re
             const int n1 = d.n1, n2 = d.n2;
             const int par = (int)(sc->iter & 1u);
             const Side<DT> src = a.side[par];
-            const float a4 = (float)sc->a4;
+            const float a4 = (float)sc->a4, gt = a.c.zt_step;
             // z as sweep A stored it in this iteration, or evaluated again
             const float *zb = sc->zstore ? a.c.zbuf : nullptr;
             const uint32_t N = (uint32_t)d.plane;
@@ -166,7 +166,7 @@ __global__ __launch_bounds__(kFbThreads) void k_fb_hist(const CubeArgs<DT> *__re
                     if (q + (uint32_t)(u * kFbThreads) >= q1) break;
                     const float y4 = y4_of(y4s[u], a4);
                     if (act0) add(0, pre0, zs_of(sv[u], y4));
-                    if (act1) add(1, pre1, zt_of(tv[u], y3m[u], y3c[u], y4));
+                    if (act1) add(1, pre1, zt_of(tv[u], y3m[u], y3c[u], y4, gt));
                 }
             }
         }

@@ -85,8 +85,6 @@ struct DevScalars {
     uint32_t call_limit; // iterations this call may do: the cube idles after them
     uint32_t zstore;     // sweep A of this iteration stores z_s and z_t
     uint32_t calm;       // iterations in a row whose windows all held tau
-    uint32_t zkeep;      // z is stored in every iteration (the comparison
-                         // regularizers' path, whose primal kernel always does)
     double gy4;          // step of y4: after an iteration y4 = gy4 c4 q
 };
 
@@ -296,6 +294,7 @@ struct CubeCommon {
     int tile0;          // first tile of this cube in the launch's full tile list
     int b0, nb;         // sweep B blocks of this cube: first, count
     float thr1;         // omega * step of w1
+    float zt_step;      // step size of t in z_t (the histogram passes evaluate z_t)
     float mu_lo, mu_hi;
     // sweep B's inputs by side parity (s, t, y3, y4, the y4 intermediate)
     // and their sizes, for the cache prefetch that runs beside the search

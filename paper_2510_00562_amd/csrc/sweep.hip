@@ -788,7 +788,7 @@ __global__ __launch_bounds__(NPT) void k_finalize(const char *table, int stride)
         // whether the next iteration's sweep A stores z (iter counts this one)
         const uint32_t calm = missed ? 0u : sc->calm + 1u;
         sc->calm = calm;
-        sc->zstore = (sc->zkeep || sc->iter + 1u < kZStoreIters || calm < kZStoreCalm) ? 1u : 0u;
+        sc->zstore = (sc->iter + 1u < kZStoreIters || calm < kZStoreCalm) ? 1u : 0u;
     }
     // the three block sums at once, in the order of block_sum: a butterfly
     // within each wavefront, then the wavefronts in order (thread 0)
@@ -1045,6 +1045,7 @@ void cube_entry_t(CubeArgs<DT> *a, const Dims &d, const float *v, void *ws, cons
     }
     c.b0 = b0;
     c.thr1 = (float)(omega * 0.25);
+    c.zt_step = kStepT;
     c.mu_lo = (float)mu_lo;
     c.mu_hi = (float)mu_hi;
     a->side[0] = side_of<DT>(ws, L, 0);

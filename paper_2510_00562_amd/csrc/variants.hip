@@ -13,10 +13,12 @@
 // histogram passes and finalize read):
 //   primal kernel: u+ = P_box(u - g_u (A^T y1 + y4)) into the other u buffer,
 //                  the inputs z_s = s - y4 and z_t = t - g_t (D_v^T y3 + y4)
-//                  of the two l1-ball projections (stored: the histogram
-//                  passes of a missed window read them), and per block (a
-//                  "tile" of the search) the window statistics, the window
-//                  candidates and the FP64 partials of the stopping rule;
+//                  of the two l1-ball projections (stored in the iterations
+//                  in which a window is likely to miss, for the histogram
+//                  passes; otherwise they evaluate them again from the
+//                  state), and per block (a "tile" of the search) the window
+//                  statistics, the window candidates and the FP64 partials
+//                  of the stopping rule;
 //   window search and three histogram passes (select.hip, fallback.hip):
 //                  the exact thresholds tau_s, tau_t;
 //   dual kernel:   s+, t+ (soft thresholds of z_s, z_t, evaluated again from
@@ -103,22 +105,10 @@ __device__ __forceinline__ float dT(const Dims &d, const float *pv, const float 
 }
 
 // The inputs z_s = s - y4 and z_t = t - g_t (D_v^T y3 + y4) of the two
-// l1-ball projections at a voxel of row i, y4 = a4 q, from the loaded
-// values y3m = y3(i - 1) and y3c = y3(i) (the rows that do not exist are
-// masked here). Both kernels evaluate them with these operations, so the
-// dual kernel's values are the primal kernel's bit for bit.
-__device__ __forceinline__ float var_dvt(int i, int n1, float y3m, float y3c)
-{
-    float x = 0.f;
-    if (i >= 1) x += y3m;
-    if (i <= n1 - 2) x -= y3c;
-    return x;
-}
-__device__ __forceinline__ float var_zs(float s, float y4) { return s - y4; }
-__device__ __forceinline__ float var_zt(float t, float dvt, float y4, float gt)
-{
-    return __builtin_fmaf(-gt, dvt + y4, t);
-}
+// l1-ball projections, y4 = a4 q, come from y4_of, zs_of and zt_of (with
+// the step g_t), the operations every kernel that evaluates them uses: the
+// primal and dual kernels here and the histogram passes of a missed window,
+// so the values are bit-identical wherever they are evaluated.
 
 // Sums of 8 FP64 values over a block of NT threads in a fixed order; valid
 // in thread 0.
@@ -155,6 +145,7 @@ __global__ __launch_bounds__(VTP) void k_var_primal(VarArgs a)
     const float *u = a.u[par], *t = a.t[par], *y3 = a.y3[par], *qo = a.q[par];
     float *un = a.u[par ^ 1];
     const float a4 = (float)sc->a4;
+    const bool zst = sc->zstore != 0u;  // z kept for the histogram passes
     const float *y1v = a.y1, *y1h = a.y1 + N;
     float wlo[2], whi[2];
     bool won[2];
@@ -180,16 +171,18 @@ __global__ __launch_bounds__(VTP) void k_var_primal(VarArgs a)
             if (k >= 1) g += dT(d, y1v, y1h, k - 1, i, j);
             if (k <= d.n3 - 2) g -= dT(d, y1v, y1h, k, i, j);
             if (a.P == 4) g += a.omega * dT(d, a.y1 + 2 * N, a.y1 + 3 * N, k, i, j);
-            const float y4 = a4 * qo[q];
+            const float y4 = y4_of(qo[q], a4);
             const float uo = u[q];
             const float x = uo - a.gu * (g + y4);
             const float nu = fminf(fmaxf(x, a.mu_lo), a.mu_hi);
             un[q] = nu;
             const float y3m = i >= 1 ? y3[q - d.n2] : 0.f, y3c = i <= d.n1 - 2 ? y3[q] : 0.f;
-            z[0] = var_zs(a.s[q], y4);
-            z[1] = var_zt(t[q], var_dvt(i, d.n1, y3m, y3c), y4, a.gt);
-            a.z[q] = z[0];
-            a.z[N + q] = z[1];
+            z[0] = zs_of(a.s[q], y4);
+            z[1] = zt_of(t[q], y3m, y3c, y4, a.gt);
+            if (zst) {
+                a.z[q] = z[0];
+                a.z[N + q] = z[1];
+            }
             const double dl = (double)nu - (double)uo;
             du2 += dl * dl;
             u2 += (double)uo * (double)uo;
@@ -278,6 +271,7 @@ __global__ __launch_bounds__(VTP) void k_var_primal4(VarArgs a)
     const float *u = a.u[par], *t = a.t[par], *y3 = a.y3[par], *qo = a.q[par];
     float *un = a.u[par ^ 1];
     const float a4 = (float)sc->a4;
+    const bool zst = sc->zstore != 0u;  // z kept for the histogram passes
     const float *y1v = a.y1, *y1h = a.y1 + N;
     float wlo[2], whi[2];
     bool won[2];
@@ -312,11 +306,11 @@ __global__ __launch_bounds__(VTP) void k_var_primal4(VarArgs a)
                 if (k >= 1) gg += gm[e];
                 if (k <= d.n3 - 2) gg -= gk[e];
                 if (a.P == 4) gg += a.omega * go[e];
-                const float y4 = a4 * qv.x[e];
+                const float y4 = y4_of(qv.x[e], a4);
                 const float x = uo.x[e] - a.gu * (gg + y4);
                 nu.x[e] = fminf(fmaxf(x, a.mu_lo), a.mu_hi);
-                zs.x[e] = var_zs(sv.x[e], y4);
-                zt.x[e] = var_zt(tv.x[e], var_dvt(i, d.n1, y3m.x[e], y3c.x[e]), y4, a.gt);
+                zs.x[e] = zs_of(sv.x[e], y4);
+                zt.x[e] = zt_of(tv.x[e], y3m.x[e], y3c.x[e], y4, a.gt);
                 z[0][e] = zs.x[e];
                 z[1][e] = zt.x[e];
                 const double dl = (double)nu.x[e] - (double)uo.x[e];
@@ -324,8 +318,10 @@ __global__ __launch_bounds__(VTP) void k_var_primal4(VarArgs a)
                 u2 += (double)uo.x[e] * (double)uo.x[e];
             }
             st4(un + q, nu);
-            st4(a.z + q, zs);
-            st4(a.z + N + q, zt);
+            if (zst) {
+                st4(a.z + q, zs);
+                st4(a.z + N + q, zt);
+            }
         }
 #pragma unroll
         for (int f = 0; f < 2; ++f)
@@ -386,12 +382,12 @@ __global__ __launch_bounds__(VTD) void k_var_dual(VarArgs a)
         int k, i, j;
         coords(d, q, k, i, j);
         // z_s, z_t here as the primal kernel evaluated them
-        const float y4 = a4 * qo[q], y3c = y3o[q];
+        const float y4 = y4_of(qo[q], a4), y3c = y3o[q];
         const float y3m = i >= 1 ? y3o[q - d.n2] : 0.f;
-        const float so = a.s[q], sn = soft_d(var_zs(so, y4), ts);
+        const float so = a.s[q], sn = soft_d(zs_of(so, y4), ts);
         a.s[q] = sn;
         const float sp = 2.f * sn - so;
-        const float tq = soft_d(var_zt(to[q], var_dvt(i, d.n1, y3m, y3c), y4, a.gt), tt);
+        const float tq = soft_d(zt_of(to[q], y3m, i <= d.n1 - 2 ? y3c : 0.f, y4, a.gt), tt);
         tn[q] = tq;
         const float tp = 2.f * tq - to[q];
         // y3 += g_y D_v t' (t' one row down from its own z_t and old t); the
@@ -399,8 +395,8 @@ __global__ __launch_bounds__(VTD) void k_var_dual(VarArgs a)
         float y3x = y3c;
         if (i <= d.n1 - 2) {
             const int64_t qd = q + d.n2;
-            const float y4d = a4 * qo[qd], y3d = i + 1 <= d.n1 - 2 ? y3o[qd] : 0.f;
-            const float ztd = var_zt(to[qd], var_dvt(i + 1, d.n1, y3c, y3d), y4d, a.gt);
+            const float y4d = y4_of(qo[qd], a4), y3d = i + 1 <= d.n1 - 2 ? y3o[qd] : 0.f;
+            const float ztd = zt_of(to[qd], y3c, y3d, y4d, a.gt);
             const float tp1 = 2.f * soft_d(ztd, tt) - to[qd];
             y3x = y3c + a.gy * (tp1 - tp);
         }
@@ -481,10 +477,10 @@ __global__ __launch_bounds__(VTD) void k_var_dual4(VarArgs a)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             // z_s, z_t here as the primal kernel evaluated them
-            const float y4 = a4 * qv.x[e];
-            sn.x[e] = soft_d(var_zs(so.x[e], y4), ts);
+            const float y4 = y4_of(qv.x[e], a4);
+            sn.x[e] = soft_d(zs_of(so.x[e], y4), ts);
             sp.x[e] = 2.f * sn.x[e] - so.x[e];
-            tq.x[e] = soft_d(var_zt(tov.x[e], var_dvt(i, d.n1, y3m.x[e], y3c.x[e]), y4, a.gt), tt);
+            tq.x[e] = soft_d(zt_of(tov.x[e], y3m.x[e], ei ? y3c.x[e] : 0.f, y4, a.gt), tt);
             tp.x[e] = 2.f * tq.x[e] - tov.x[e];
         }
         st4(a.s + q, sn);
@@ -499,7 +495,7 @@ __global__ __launch_bounds__(VTD) void k_var_dual4(VarArgs a)
             if (i + 1 <= d.n1 - 2) y3d = ld4(y3o + qd);
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const float ztd = var_zt(td.x[e], var_dvt(i + 1, d.n1, y3c.x[e], y3d.x[e]), a4 * qd4.x[e], a.gt);
+                const float ztd = zt_of(td.x[e], y3c.x[e], y3d.x[e], y4_of(qd4.x[e], a4), a.gt);
                 const float tp1 = 2.f * soft_d(ztd, tt) - td.x[e];
                 y3x.x[e] = y3c.x[e] + a.gy * (tp1 - tp.x[e]);
             }
@@ -579,7 +575,6 @@ __global__ __launch_bounds__(VT) void k_var_init(VarArgs a, double eps, double t
         z.sel[1].radius = beta;
         z.sel[0].done = z.sel[1].done = 1u;  // no search pending
         z.zstore = 1u;
-        z.zkeep = 1u;
         z.gy4 = gy4;
         *a.sc = z;
     }
@@ -749,14 +744,22 @@ VarArgs var_args(const Dims &d, const geo_params *p, const float *v, void *ws, V
 
 // Host image of the launch table entry: the fields the window search, the
 // histogram passes and the finalize read. The tile geometry and the sweep B
-// prefetch of the main solver stay zero, and so do the state sides: the
-// passes read z from the z arrays (zkeep), never from the state.
+// prefetch of the main solver stay zero. The state sides hold the arrays
+// from which the histogram passes evaluate z_s and z_t (s, t, y3, the y4
+// residual) when the primal kernel did not store them.
 void var_table_entry(CubeEntry *e, const VarArgs &a, const VarLayout &L, void *ws)
 {
     memset(e, 0, sizeof *e);
     CubeArgs<float> *x = reinterpret_cast<CubeArgs<float> *>(e->bytes);
     char *b = (char *)ws;
+    for (int p = 0; p < 2; ++p) {
+        x->side[p].s = a.s;
+        x->side[p].t = a.t[p];
+        x->side[p].y3 = a.y3[p];
+        x->side[p].y4 = a.q[p];
+    }
     CubeCommon &c = x->c;
+    c.zt_step = a.gt;
     c.d = a.d;
     c.v = a.v;
     c.sc = a.sc;

@@ -329,3 +329,42 @@ def test_benchmark_cube_in_the_bench_configuration(ora, variant):
     assert errs["u"] <= 1e-5 and max(errs.values()) <= 1e-4, errs
     rel, r, ts, tt = S.trace[-1]
     assert res.tau_s == pytest.approx(ts, rel=1e-5) and res.tau_t == pytest.approx(tt, rel=1e-5)
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+@pytest.mark.parametrize("shape", [(16, 48, 60), (16, 48, 64)])
+def test_late_miss_evaluates_z_from_the_state(ora, variant, shape):
+    """A window that misses long after the start (the radii of (16), (17)
+    change between calls, which moves both thresholds) is found by histogram
+    passes that evaluate z_s and z_t from the variant's state: the primal
+    kernel stores them only in the first iterations and after recent misses
+    (three calm iterations before the change make sure it did not). The
+    thresholds and iterates must still follow the oracle; one-voxel and
+    four-voxel kernels."""
+    n0 = 30
+    announce(f"{NAMES[variant]}: late missed windows {shape}")
+    c = problem(shape, 19)
+    prm = dict(eps=c["eps"], alpha=c["alpha"], beta=c["beta"], omega=0.05)
+    geo, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, variant)
+    res = geo.geo_step(dims, p, vd, ws, n0 - 3)
+    assert res.iters == n0 - 3
+    calm = [geo.geo_step(dims, p, vd, ws, 1).fallback_passes for _ in range(3)]
+    assert calm == [0, 0, 0], calm
+    S = ora.VariantSolver(c["v"], prm["eps"], prm["alpha"], prm["beta"], variant, omega=prm["omega"])
+    S.step(n0)
+    p.alpha, p.beta = 0.5 * prm["alpha"], 0.6 * prm["beta"]
+    S.params.alpha, S.params.beta = p.alpha, p.beta
+    misses, taus = [], []
+    for _ in range(3):
+        r = geo.geo_step(dims, p, vd, ws, 1)
+        misses.append(r.fallback_passes)
+        taus.append((r.tau_s, r.tau_t))
+    S.step(3)
+    print(f"{NAMES[variant]}: missed windows after the change: {misses}", flush=True)
+    assert misses[0] >= 1
+    for k, (g, o) in enumerate(zip(taus, S.trace[n0:])):
+        assert g[0] == pytest.approx(o[2], rel=1e-5, abs=1e-12), (k, "tau_s")
+        assert g[1] == pytest.approx(o[3], rel=1e-5, abs=1e-12), (k, "tau_t")
+    g = get_state(geo, dims, p, ws, vd, shape, variant)
+    errs = {k: rel_l2(g[k], S.state[k]) for k in STATE if np.linalg.norm(S.state[k]) > 0}
+    assert errs["u"] <= 1e-5 and max(errs.values()) <= 1e-4, errs
