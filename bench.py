@@ -78,6 +78,8 @@ def parse():
     ap.add_argument("--dual", choices=("f32", "bf16"), default="f32",
                     help="storage of the dual variables y1..y4")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--compare", action="store_true",
+                    help="quality: also solve the cases with SSTV, HSSTV1 and HSSTV2 (Sec. IV-A)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles",
                                                        "sweep_a_traffic_256x256x128.txt"))
@@ -516,7 +518,61 @@ def bench_quality(args):
         "seconds": el,
         "voxel_iterations_per_s": vox_it / el,
     }
+    if args.compare:
+        out["comparison"] = quality_comparison(runs, best)
     print(json.dumps(out), flush=True)
+
+
+def quality_comparison(runs, best):
+    """The comparison of Sec. IV-A on the same cubes: SSTV, HSSTV1 and
+    HSSTV2 in place of GeoSSTV in the same problem, solved by the same P-PDS
+    to the same stopping rule (geo_solve, one cube at a time), with the
+    best MPSNR over the same omega grid for HSSTV (the paper does not state
+    the weight it used; SSTV has none)."""
+    import numpy as np
+    import torch
+
+    import paper_2510_00562_amd as geo
+    from synth.quality import mpsnr, mssim
+
+    cubes = {}
+    for name, case, omega, c in runs:
+        cubes[(name, case)] = c
+    methods = (("sstv", geo.REGULARIZERS["sstv"], (0.0,)),
+               ("hsstv1", geo.REGULARIZERS["hsstv1"], (0.01, 0.03, 0.05)),
+               ("hsstv2", geo.REGULARIZERS["hsstv2"], (0.01, 0.03, 0.05)))
+    per_case = {}
+    t0 = time.perf_counter()
+    for (name, case), c in cubes.items():
+        key = f"{name}/case{case}"
+        v = torch.from_numpy(np.ascontiguousarray(c["v"], dtype=np.float32)).cuda()
+        d = geo.dims_of(v.shape)
+        ent = {"geosstv": best[key]}
+        for mname, reg, omegas in methods:
+            top = None
+            for omega in omegas:
+                p = geo.params(c["eps"], c["alpha"], c["beta"], omega=omega, tol=1e-5, max_iter=20000,
+                               regularizer=reg)
+                ws = geo.Workspace(geo.geo_workspace_size(d, p))
+                u, s, t = (torch.empty_like(v) for _ in range(3))
+                r = geo.geo_solve(d, p, v, u, s, t, ws)
+                uh = u.cpu().numpy().astype(np.float64)
+                row = {"omega": omega, "iters": r.iters, "converged": bool(r.converged),
+                       "mpsnr": mpsnr(uh, c["u_clean"]), "mssim": mssim(uh, c["u_clean"])}
+                if top is None or row["mpsnr"] > top["mpsnr"]:
+                    top = row
+                del ws, u, s, t
+            ent[mname] = top
+        per_case[key] = ent
+        print(f"[quality] {key}: " + ", ".join(f"{m} {e['mpsnr']:.2f} dB" for m, e in ent.items()),
+              file=sys.stderr, flush=True)
+    names = ("geosstv", "sstv", "hsstv1", "hsstv2")
+    return {"per_case": per_case,
+            "mean_mpsnr": {m: float(np.mean([e[m]["mpsnr"] for e in per_case.values()])) for m in names},
+            "mean_mssim": {m: float(np.mean([e[m]["mssim"] for e in per_case.values()])) for m in names},
+            "cases_won_mpsnr": {m: sum(1 for e in per_case.values()
+                                       if max(names, key=lambda x: e[x]["mpsnr"]) == m) for m in names},
+            "seconds": time.perf_counter() - t0}
 
 
 def bench_realshape(args):
