@@ -368,3 +368,24 @@ def test_late_miss_evaluates_z_from_the_state(ora, variant, shape):
     g = get_state(geo, dims, p, ws, vd, shape, variant)
     errs = {k: rel_l2(g[k], S.state[k]) for k in STATE if np.linalg.norm(S.state[k]) > 0}
     assert errs["u"] <= 1e-5 and max(errs.values()) <= 1e-4, errs
+
+
+@pytest.mark.parametrize("variant", [1, 3])
+def test_zero_iterations_and_state_round_trip(variant):
+    """A state loaded after an odd number of iterations (y3 and the y4
+    residual live on two sides, like u and t; the iteration parity picks the
+    current one) reads back unchanged, also after a call of no iterations."""
+    shape = (6, 10, 12)
+    announce(f"{NAMES[variant]}: state round trip {shape}")
+    c = problem(shape, 23)
+    prm = radii(shape)
+    geo, dims, p, ws, vd = gpu_solver(shape, c["v"], prm, variant)
+    geo.geo_step(dims, p, vd, ws, 3)
+    st = random_vstate(shape, variant, 29)
+    for name in STATE:
+        geo.geo_state_set(dims, p, ws, name, vd, dev(st[name]))
+    res = geo.geo_step(dims, p, vd, ws, 0)
+    assert res.iters == 0
+    g = get_state(geo, dims, p, ws, vd, shape, variant)
+    for name in STATE:
+        assert np.array_equal(g[name], st[name]), name
