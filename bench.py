@@ -143,28 +143,35 @@ def read_traffic(path, cube):
     return fetch + write
 
 
-def cpu_baseline(c, seconds):
-    """The FP64 oracle on the same cube: as many full iterations as fit in
-    about `seconds` (at least 2), on all host threads."""
+def cpu_baseline(c, seconds, reg=0, what="the FP64 oracle"):
+    """The FP64 oracle on the same cube, on all host threads, timed over one
+    call of k full iterations: k grows from 2 until a call takes at least
+    half of `seconds`. One call per iteration would time the oracle's
+    per-call set-up too (its scratch, 42 doubles per voxel, is allocated and
+    first touched by every call: 0.25 instead of 0.16 s per iteration at
+    256x256x128 on 16 threads)."""
     import numpy as np
 
     import oracle
     v = np.asarray(c["v"], dtype=np.float64)
-    S = oracle.Solver(v, c["eps"], c["alpha"], c["beta"], omega=c["omega"])
-    S.step(1)  # first-touch of the oracle's buffers
-    done, t0 = 0, time.perf_counter()
+    if reg:
+        S = oracle.VariantSolver(v, c["eps"], c["alpha"], c["beta"], reg, omega=c["omega"])
+    else:
+        S = oracle.Solver(v, c["eps"], c["alpha"], c["beta"], omega=c["omega"])
+    k = 2
     while True:
-        S.step(1)
-        done += 1
+        t0 = time.perf_counter()
+        S.step(k)
         el = time.perf_counter() - t0
-        if done >= 2 and el >= seconds:
+        if el >= 0.5 * seconds or k >= 1 << 20:
             break
+        k = max(2 * k, int(k * 0.75 * seconds / max(el, 1e-6)))
     n = v.size
-    return {"value": n * done / el, "unit": "voxel-iterations/s",
+    n3, n1, n2 = c["shape"]
+    return {"value": n * k / el, "unit": "voxel-iterations/s",
             "cores": int(oracle.threads_for(n)), "kind": "oracle",
-            "sample": f"{done} full iterations of the FP64 oracle on the same "
-                      f"{c['shape'][1]}x{c['shape'][2]}x{c['shape'][0]} cube "
-                      f"({el:.1f} s)"}
+            "sample": f"{k} full iterations of {what} in one call on the same "
+                      f"{n1}x{n2}x{n3} cube ({el:.1f} s)"}
 
 
 def main():
@@ -709,21 +716,8 @@ def bench_regularizer(args):
                  "tau_t": res.tau_t, "iters": res.total_iters},
     }
     if not args.no_cpu_baseline:
-        import oracle
-        vv = np.asarray(c["v"], dtype=np.float64)
-        S = oracle.VariantSolver(vv, c["eps"], c["alpha"], c["beta"], reg, omega=c["omega"])
-        S.step(1)
-        done, t1 = 0, time.perf_counter()
-        while True:
-            S.step(1)
-            done += 1
-            e2 = time.perf_counter() - t1
-            if done >= 2 and e2 >= args.cpu_seconds:
-                break
-        out["cpu_baseline"] = {"value": N * done / e2, "unit": "voxel-iterations/s",
-                               "cores": int(oracle.threads_for(N)), "kind": "oracle",
-                               "sample": f"{done} full iterations of the FP64 oracle "
-                                         f"({args.regularizer}) on the same cube ({e2:.1f} s)"}
+        out["cpu_baseline"] = cpu_baseline(c, args.cpu_seconds, reg=reg,
+                                           what=f"the FP64 oracle ({args.regularizer})")
     print(json.dumps(out), flush=True)
 
 
